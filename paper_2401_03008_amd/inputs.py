@@ -1,0 +1,166 @@
+"""Seeded synthetic initial data: cell-centred rho, v, p and face-staggered B.
+
+This module holds only the definitions of the test problems.  It performs no
+step of the solver (no conversion to conserved variables, no reconstruction,
+no flux), so both the GPU path and the CPU oracle can start from the same
+inputs.
+
+Layout: numpy float64 arrays of shape (nz, ny, nx), x fastest.  Cell centres
+are at ((i+1/2) dx, (j+1/2) dy, (k+1/2) dz); the face array bf[d] holds B_d at
+the +d face of each cell, e.g. bf[0][k, j, i] = B_x((i+1) dx, (j+1/2) dy,
+(k+1/2) dz).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+GAMMA_AD = 4.0 / 3.0
+
+
+def cpa_alfven_speed(rho=1.0, p=1.0, B0=1.0, eta=1.0, gam=GAMMA_AD):
+    """Exact speed of the large-amplitude circularly polarised Alfven wave
+    (Sec. 4, equation for v_A^2; rho h = rho + gam/(gam-1) p)."""
+    rhoh = rho + gam / (gam - 1.0) * p
+    a = rhoh + B0 * B0 * (1.0 + eta * eta)
+    x = 2.0 * eta * B0 * B0 / a
+    return math.sqrt(B0 * B0 / a / (0.5 * (1.0 + math.sqrt(1.0 - x * x))))
+
+
+def cpa_basis(diagonal: bool):
+    """Right-handed orthonormal (X, Y, Z) with X the propagation direction.
+
+    Axis case: X = x.  Diagonal case: X = (1,1,1)/sqrt3, Y = (-1,1,0)/sqrt2,
+    Z = X x Y.  The paper rotates the wave onto the box diagonal (Sec. 4);
+    any right-handed basis with this X is an equally exact wave."""
+    if not diagonal:
+        return np.eye(3)
+    X = np.array([1.0, 1.0, 1.0]) / math.sqrt(3.0)
+    Y = np.array([-1.0, 1.0, 0.0]) / math.sqrt(2.0)
+    Z = np.cross(X, Y)
+    return np.stack([X, Y, Z])
+
+
+def cpa_wavevector(diagonal: bool, L=(1.0, 1.0, 1.0)):
+    if diagonal:
+        return np.array([2 * math.pi / L[0], 2 * math.pi / L[1], 2 * math.pi / L[2]])
+    return np.array([2 * math.pi / L[0], 0.0, 0.0])
+
+
+def cpa_period(diagonal: bool, rho=1.0, p=1.0, B0=1.0, eta=1.0, gam=GAMMA_AD,
+               L=(1.0, 1.0, 1.0)):
+    """T = 2 pi / (|k| v_A)."""
+    k = np.linalg.norm(cpa_wavevector(diagonal, L))
+    return 2 * math.pi / (k * cpa_alfven_speed(rho, p, B0, eta, gam))
+
+
+def _fields_at(x, y, z, t, diagonal, rho, p, B0, eta, gam, L):
+    XYZ = cpa_basis(diagonal)
+    kv = cpa_wavevector(diagonal, L)
+    va = cpa_alfven_speed(rho, p, B0, eta, gam)
+    phi = kv[0] * x + kv[1] * y + kv[2] * z - np.linalg.norm(kv) * va * t
+    c, s = np.cos(phi), np.sin(phi)
+    B = [B0 * XYZ[0][d] + eta * B0 * (c * XYZ[1][d] + s * XYZ[2][d]) for d in range(3)]
+    v = [-va * eta * (c * XYZ[1][d] + s * XYZ[2][d]) for d in range(3)]
+    return v, B
+
+
+def cpa(n, diagonal=True, t=0.0, rho=1.0, p=1.0, B0=1.0, eta=1.0, gam=GAMMA_AD,
+        L=(1.0, 1.0, 1.0)):
+    """Exact CPA wave at time t on an (nz, ny, nx) grid.
+
+    n is an int (cube) or (nx, ny, nz).  Returns (prim5, bf, Bc): prim5 =
+    [rho, vx, vy, vz, p] at cell centres, bf = face B point-sampled at face
+    centres, Bc = the exact B at cell centres (for error measurement)."""
+    nx, ny, nz = (n, n, n) if np.isscalar(n) else n
+    dx, dy, dz = L[0] / nx, L[1] / ny, L[2] / nz
+    xc = (np.arange(nx) + 0.5) * dx
+    yc = (np.arange(ny) + 0.5) * dy
+    zc = (np.arange(nz) + 0.5) * dz
+    xf, yf, zf = (np.arange(nx) + 1.0) * dx, (np.arange(ny) + 1.0) * dy, (np.arange(nz) + 1.0) * dz
+    Z, Y, X = np.meshgrid(zc, yc, xc, indexing="ij")
+    v, Bc = _fields_at(X, Y, Z, t, diagonal, rho, p, B0, eta, gam, L)
+    shape = (nz, ny, nx)
+    prim5 = [np.full(shape, rho), v[0], v[1], v[2], np.full(shape, p)]
+    bf = []
+    for d in range(3):
+        coords = [xc, yc, zc]
+        coords[d] = [xf, yf, zf][d]
+        Zf, Yf, Xf = np.meshgrid(coords[2], coords[1], coords[0], indexing="ij")
+        _, Bd = _fields_at(Xf, Yf, Zf, t, diagonal, rho, p, B0, eta, gam, L)
+        bf.append(np.ascontiguousarray(Bd[d]))
+    prim5 = [np.ascontiguousarray(a, dtype=np.float64) for a in prim5]
+    return prim5, bf, [np.ascontiguousarray(b) for b in Bc]
+
+
+def turbulence(n, sigma0=10.0, beta0=0.1, B0=1.0, nmodes=16, kmax=2, gamma_max=5.0,
+               seed=20240103, L=(1.0, 1.0, 1.0)):
+    """Decaying Alfvenic turbulence, 3D synthetic stand-in for the paper's 2D
+    random-phase set-up (Sec. 5): uniform B0 along z, rho0 = B0^2/sigma0,
+    p0 = beta0 B0^2 / 2, plus nmodes random-phase transverse modes with
+    integer wave numbers in [-kmax, kmax]^3, (n_x, n_y) != 0, one of each +-k
+    pair.
+
+    Magnetic perturbation: edge vector potential A_z = sum sin(k.x + phi_B) /
+    |k_perp| at (x_{i+1/2}, y_{j+1/2}, z_k); face B = its discrete curl
+    (B_x = dA_z/dy, B_y = -dA_z/dx), so div B vanishes to round-off; A is
+    rescaled so that max |dB| = B0.  Velocity: 4-velocity u = -sum e_k
+    cos(k.x + phi_v), e_k = (k_hat x z)/|k_hat x z|, rescaled so that
+    max Gamma = gamma_max, v = u / sqrt(1 + u^2).
+
+    Returns (prim5, bf)."""
+    nx, ny, nz = (n, n, n) if np.isscalar(n) else n
+    rng = np.random.default_rng(seed)
+    cand = []
+    for a in range(-kmax, kmax + 1):
+        for b in range(-kmax, kmax + 1):
+            for c in range(-kmax, kmax + 1):
+                if a > 0 or (a == 0 and b > 0):
+                    cand.append((a, b, c))
+    pick = rng.choice(len(cand), size=nmodes, replace=False)
+    modes = [cand[i] for i in sorted(pick)]
+    phiB = rng.uniform(0, 2 * math.pi, nmodes)
+    phiv = rng.uniform(0, 2 * math.pi, nmodes)
+
+    dx, dy, dz = L[0] / nx, L[1] / ny, L[2] / nz
+    xc = (np.arange(nx) + 0.5) * dx
+    yc = (np.arange(ny) + 0.5) * dy
+    zc = (np.arange(nz) + 0.5) * dz
+    xf, yf = (np.arange(nx) + 1.0) * dx, (np.arange(ny) + 1.0) * dy
+    shape = (nz, ny, nx)
+
+    A = np.zeros(shape)
+    ux, uy = np.zeros(shape), np.zeros(shape)
+    Ze, Ye, Xe = np.meshgrid(zc, yf, xf, indexing="ij")
+    Zc, Yc, Xc = np.meshgrid(zc, yc, xc, indexing="ij")
+    for (a, b, c), pB, pv in zip(modes, phiB, phiv):
+        k = np.array([2 * math.pi * a / L[0], 2 * math.pi * b / L[1], 2 * math.pi * c / L[2]])
+        kp = math.hypot(k[0], k[1])
+        A += np.sin(k[0] * Xe + k[1] * Ye + k[2] * Ze + pB) / kp
+        kn = np.linalg.norm(k)
+        e = np.array([k[1], -k[0]]) / kn
+        e /= np.linalg.norm(e)
+        cv = np.cos(k[0] * Xc + k[1] * Yc + k[2] * Zc + pv)
+        ux -= e[0] * cv
+        uy -= e[1] * cv
+    # face B from the discrete curl of A_z (A at (i+1/2, j+1/2, k))
+    bx = (A - np.roll(A, 1, axis=1)) / dy
+    by = -(A - np.roll(A, 1, axis=2)) / dx
+    # rescale so that max |dB| at cell centres (face averages) equals B0
+    bxc = 0.5 * (bx + np.roll(bx, 1, axis=2))
+    byc = 0.5 * (by + np.roll(by, 1, axis=1))
+    scale = B0 / np.sqrt(bxc ** 2 + byc ** 2).max()
+    bx *= scale
+    by *= scale
+    bz = np.full(shape, B0)
+    umax = math.sqrt(gamma_max ** 2 - 1.0)
+    us = umax / np.sqrt(ux ** 2 + uy ** 2).max()
+    ux *= us
+    uy *= us
+    lor = np.sqrt(1.0 + ux ** 2 + uy ** 2)
+    rho0 = B0 * B0 / sigma0
+    p0 = 0.5 * beta0 * B0 * B0
+    prim5 = [np.full(shape, rho0), ux / lor, uy / lor, np.zeros(shape), np.full(shape, p0)]
+    prim5 = [np.ascontiguousarray(a) for a in prim5]
+    return prim5, [np.ascontiguousarray(bx), np.ascontiguousarray(by), bz]
