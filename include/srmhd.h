@@ -1,0 +1,176 @@
+/*
+ * srmhd.h -- C ABI of libsrmhd.so: one SSP-RK3 step of 3D ideal special-
+ * relativistic MHD (flat space, Cartesian, periodic box) on an MI355X.
+ *
+ * The method follows Del Zanna et al., "A GPU-Accelerated Modern Fortran
+ * Version of the ECHO Code for Relativistic Magnetohydrodynamics" (arXiv
+ * 2401.03008): the ideal SRMHD system and its conserved variables (Sec. 2),
+ * the semi-discrete point-value scheme with face-staggered B and edge electric
+ * fields, and the five parts of each Runge-Kutta substep -- INT + Newton
+ * inversion, REC + upwind fluxes + stored fast speeds, DER, UCT, RK update with
+ * a timestep from the global maximum of the speeds once per step (Sec. 3).
+ * Formulas the paper leaves to its references are taken from the published
+ * methods named at each entry point.
+ *
+ * Conventions for every entry point
+ *   - Device pointers are HIP device addresses on the context's device; host
+ *     pointers are marked (host).  Every grid array is nx*ny*nz doubles,
+ *     contiguous, x fastest: a[(k*ny + j)*nx + i].
+ *   - bface[d] holds B_d on the +d face of each cell (x_{i+1/2} for d = 0).
+ *   - The caller owns every buffer; the library allocates no device memory.
+ *     Scratch comes from srmhd_buffers.work (size from srmhd_work_bytes).
+ *   - All GPU work is enqueued on the stream given to srmhd_create, in order;
+ *     only calls documented as "syncs" wait for the stream.
+ *   - Return value: SRMHD_OK (0) or a negative SRMHD_E_* code.  Argument
+ *     errors are detected on the host before any launch.  Failures detected on
+ *     the device set a device error word that the next syncing call returns.
+ *     srmhd_last_error gives the message of the last failure of a context.
+ *   - A context is used from one host thread at a time.
+ */
+#ifndef SRMHD_H
+#define SRMHD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SRMHD_OK 0
+#define SRMHD_E_INVAL (-1)     /* bad argument or configuration */
+#define SRMHD_E_HIP (-2)       /* a HIP runtime call failed */
+#define SRMHD_E_C2P (-3)       /* Newton inversion failed in some cell */
+#define SRMHD_E_NONFINITE (-4) /* non-finite conserved data or timestep */
+#define SRMHD_E_STATE (-5)     /* call out of order (e.g. step before init) */
+
+enum { SRMHD_HLL = 0, SRMHD_LLF = 1 };
+enum { SRMHD_FP64 = 0, SRMHD_MIXED = 1 };
+enum { SRMHD_GUESS_PREV = 0, SRMHD_GUESS_MLP = 1, SRMHD_GUESS_COLD = 2 };
+
+/* Device error word bits (srmhd_diag.error_word). */
+#define SRMHD_ERRBIT_C2P 1u       /* an inversion did not converge */
+#define SRMHD_ERRBIT_NONFINITE 2u /* non-finite or unusable conserved input */
+#define SRMHD_ERRBIT_DT 4u        /* timestep not finite and positive */
+#define SRMHD_ERRBIT_PRESSURE 8u  /* recovered p <= 0 with no floor set */
+
+typedef struct {
+  int nx, ny, nz;   /* cells per direction, each >= 8; nx*ny*nz < 2^31 */
+  double lx, ly, lz;/* box lengths (> 0) */
+  double gamma_ad;  /* adiabatic index, 1 < gamma_ad <= 2 (4/3 in all tests) */
+  double cfl;       /* dt = cfl / max_cells sum_d max(a+,a-)_d/dx_d */
+  double dt_fixed;  /* > 0: fixed dt instead of the CFL rule */
+  int riemann;      /* SRMHD_HLL or SRMHD_LLF */
+  int precision;    /* SRMHD_FP64, or SRMHD_MIXED: REC + face fluxes in FP32 */
+  int guess;        /* SRMHD_GUESS_PREV, _MLP (needs srmhd_set_mlp) or _COLD */
+  int newton_maxit; /* Newton iteration cap, 1..1000 (50) */
+  double newton_tol;/* relative step tolerance on W (1e-14) */
+  double pfloor;    /* pressure floor as a fraction of rho; 0 = none */
+  int collect_stats;/* 1: Newton histogram / counters per inversion */
+} srmhd_config;
+
+typedef struct {
+  double *cons[5];   /* D, Sx, Sy, Sz, U at cell centres (device) */
+  double *bface[3];  /* staggered B_x, B_y, B_z (device) */
+  double *guess_w;   /* per-cell Newton guess / converged W (device) */
+  void *work;        /* scratch (device), >= srmhd_work_bytes, 256-B aligned */
+  size_t work_bytes;
+} srmhd_buffers;
+
+typedef struct {
+  double t;              /* simulated time */
+  double dt;             /* last timestep */
+  long step;             /* full RK3 steps taken */
+  double amax;           /* last max_cells sum_d max(a+,a-)_d/dx_d */
+  double divb_max;       /* max over cells |div_h B| */
+  double sums[8];        /* sum over cells of D, Sx, Sy, Sz, U, Bx, By, Bz(face) */
+  long newton_iters;     /* Newton iterations summed over inversions */
+  long newton_calls;     /* inversions counted */
+  long newton_hist[32];  /* histogram of per-inversion iteration counts */
+  long c2p_failures;     /* inversions that did not converge */
+  long recon_fallbacks;  /* face states replaced by first-order values */
+  long floors;           /* pressure floors applied */
+  long mlp_fallbacks;    /* learned-guess inversions redone from the old W */
+  unsigned error_word;   /* SRMHD_ERRBIT_* accumulated since the last reset */
+} srmhd_diag;
+
+typedef struct srmhd_ctx srmhd_ctx;
+
+/* Fill *cfg with the defaults: 32^3 unit box, gamma 4/3, cfl 0.5, HLL, FP64,
+ * previous-W guess, maxit 50, tol 1e-14, no floor, stats on. */
+int srmhd_config_default(srmhd_config *cfg);
+
+/* Size in bytes of the scratch a context with *cfg needs.  Validates *cfg;
+ * no GPU call. */
+int srmhd_work_bytes(const srmhd_config *cfg, size_t *bytes);
+
+/* Create a context over caller-owned device buffers.  stream is a
+ * hipStream_t (NULL = default stream); the current HIP device becomes the
+ * context's device.  The library keeps the pointers, never frees them. */
+int srmhd_create(const srmhd_config *cfg, const srmhd_buffers *buf,
+                 void *stream, srmhd_ctx **out);
+
+/* Set the state from cell-centred rho, vx, vy, vz, p (prim5, device) and
+ * face B (bface, device; copied into the state's face arrays).  Conserved
+ * variables follow Sec. 2 with centred B = INT (face average) of bface; the
+ * guess W is set to rho h Gamma^2.  Resets t, step, counters and the error
+ * word. */
+int srmhd_init_from_prims(srmhd_ctx *ctx, const double *const prim5[5],
+                          const double *const bface[3]);
+
+/* Enqueue nsteps full SSP-RK3 steps (Shu & Osher 1988) of the Sec. 3 scheme:
+ * per stage INT + Newton inversion, MP5 REC (Suresh & Huynh 1997) of rho, v,
+ * p and transverse centred B, HLL/LLF face fluxes with the Del Zanna et al.
+ * (2003) fast-speed bound, UCT edge fields (Londrillo & Del Zanna 2004),
+ * flux divergence and curl; dt from the first stage's speeds.  Asynchronous;
+ * t and dt stay on the device. */
+int srmhd_step(srmhd_ctx *ctx, int nsteps);
+
+/* Spatial operator on the current state: INT + inversion, then
+ * rhs[0..4] = -sum_d (Fhat(+d face) - Fhat(-d face))/dx_d at the centres and
+ * rhs[5+d] = -(curl_h E)_d on the d faces (Sec. 3 semi-discrete equations);
+ * *amax_dev (device, one double) receives max_cells sum_d max(a+,a-)_d/dx_d.
+ * Updates the guess W.  Asynchronous. */
+int srmhd_rhs(srmhd_ctx *ctx, double *const rhs[8], double *amax_dev);
+
+/* INT + inversion of the current state into caller device arrays
+ * prim[0..7] = rho, vx, vy, vz, p, Bcx, Bcy, Bcz.  Updates the guess W.
+ * Asynchronous. */
+int srmhd_get_primitives(srmhd_ctx *ctx, double *const prim[8]);
+
+/* Diagnostics (host struct).  Syncs the stream.  Sums and div B use fixed-
+ * order reductions (bitwise reproducible).  Returns SRMHD_E_C2P /
+ * SRMHD_E_NONFINITE if the device error word is set (the struct is still
+ * filled). */
+int srmhd_get_diagnostics(srmhd_ctx *ctx, srmhd_diag *out);
+
+/* Clear counters and the error word.  Asynchronous. */
+int srmhd_reset_counters(srmhd_ctx *ctx);
+
+/* Simulated time and step count (host values).  get syncs; set is
+ * asynchronous.  With the caller-owned state arrays these make a
+ * checkpoint. */
+int srmhd_get_time(srmhd_ctx *ctx, double *t, long *step, double *dt);
+int srmhd_set_time(srmhd_ctx *ctx, double t, long step);
+
+/* Per-kernel timing with HIP events recorded on the context's stream around
+ * every launch (adds a small host/queue overhead per launch; off by
+ * default).  Classes, in order: 0 inversion, 1-3 face flux x/y/z, 4-6 UCT
+ * edge x/y/z, 7 RK update, 8 timestep.  srmhd_get_kernel_times syncs and
+ * returns the accumulated milliseconds and launch counts since timing was
+ * last enabled (ms, launches: host arrays of SRMHD_NKCLASS). */
+#define SRMHD_NKCLASS 9
+int srmhd_kernel_timing(srmhd_ctx *ctx, int enable);
+int srmhd_get_kernel_times(srmhd_ctx *ctx, double *ms, long *launches);
+
+/* Message of the last failure on ctx (NULL ctx: last creation failure). */
+const char *srmhd_last_error(const srmhd_ctx *ctx);
+const char *srmhd_strerror(int code);
+
+/* Release the context (host memory only). Syncs the stream. */
+void srmhd_destroy(srmhd_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -87,12 +87,14 @@ def lib():
         L.orc_c2p.restype = C.c_int
         L.orc_rhs.argtypes = [cp, _PP, _PP, _PP, _PD, _PP, _PP, _PP, _PP,
                               C.POINTER(Stats)]
+        L.orc_rhs_cells.argtypes = [cp, _PP, _PP, C.c_int, C.c_void_p, C.c_void_p]
         L.orc_step.argtypes = [cp, _PP, _PP, C.c_void_p, C.c_int, _PD, _PD,
                                C.POINTER(Stats)]
         L.orc_step.restype = C.c_int
         L.orc_divb_max.argtypes = [cp, _PP]
         L.orc_divb_max.restype = _D
         L.orc_sums.argtypes = [cp, _PP, _PP, _PD]
+        L.orc_num_threads.restype = C.c_int
         _lib = L
     return _lib
 
@@ -100,6 +102,10 @@ def lib():
 def _vec(x, n):
     a = np.ascontiguousarray(np.asarray(x, dtype=np.float64).reshape(n))
     return a, a.ctypes.data_as(_PD)
+
+
+def num_threads() -> int:
+    return lib().orc_num_threads()
 
 
 # ---------------------------------------------------------------- point ops
@@ -213,6 +219,14 @@ class Grid:
         lib().orc_rhs(C.byref(self.cfg), _ptrs(prim), _ptrs(bf), _ptrs(rhs),
                       C.byref(amax), None, None, None, None, C.byref(self.stats))
         return rhs, amax.value
+
+    def rhs_cells(self, prim, bf, cells):
+        """L(U) at the linear cell indices `cells` only: array (len(cells), 8)."""
+        cells = np.ascontiguousarray(cells, dtype=np.int64)
+        out = np.zeros((len(cells), 8))
+        lib().orc_rhs_cells(C.byref(self.cfg), _ptrs(prim), _ptrs(bf), len(cells),
+                            cells.ctypes.data, out.ctypes.data)
+        return out
 
     def step(self, cons, bf, W, nsteps, t=0.0):
         """Advance in place; returns (t, dt_last, nfail)."""

@@ -48,6 +48,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define MP5_ALPHA 4.0
 #define MP5_EPS 1e-10
@@ -365,6 +368,93 @@ static void rec_face(const orc_cfg *c, const double *a, int i, int j, int k, int
   *vr = orc_mp5(r);
 }
 
+static int state_ok(const double *pr) {
+  const double v2 = pr[1] * pr[1] + pr[2] * pr[2] + pr[3] * pr[3];
+  return pr[0] > 0.0 && pr[4] > 0.0 && v2 < 1.0;
+}
+
+/* Everything computed at the +face along d of cell (i,j,k). */
+typedef struct {
+  double fhat[5]; /* D, Sx, Sy, Sz, U */
+  double ap, am;
+  double v[6];    /* left vx, vy, vz; right vx, vy, vz */
+} face_out;
+
+/* REC of rho, v, p and the two transverse centred B (MP5 along d), normal B
+ * from the face, first-order fallback of an unusable side, upwind flux.
+ * Returns the number of sides that fell back (0..2). */
+static int face_solve(const orc_cfg *c, double *const *prim, double *const *bf, int i, int j,
+                      int k, int d, face_out *o) {
+  const long id = ((long)k * c->ny + j) * c->nx + i;
+  const long ip = idx_shift(c, i, j, k, d, 1);
+  double prL[8], prR[8];
+  int nfb = 0;
+  for (int n = 0; n < 8; ++n) {
+    if (n == 5 + d) continue;
+    rec_face(c, prim[n], i, j, k, d, &prL[n], &prR[n]);
+  }
+  prL[5 + d] = prR[5 + d] = bf[d][id];
+  if (!state_ok(prL)) {
+    for (int n = 0; n < 8; ++n)
+      if (n != 5 + d) prL[n] = prim[n][id];
+    ++nfb;
+  }
+  if (!state_ok(prR)) {
+    for (int n = 0; n < 8; ++n)
+      if (n != 5 + d) prR[n] = prim[n][ip];
+    ++nfb;
+  }
+  double f8[8];
+  orc_riemann(c->riemann, c->gam, prL, prR, d, f8, &o->ap, &o->am);
+  for (int n = 0; n < 5; ++n) o->fhat[n] = f8[n];
+  for (int m = 0; m < 3; ++m) {
+    o->v[m] = prL[1 + m];
+    o->v[3 + m] = prR[1 + m];
+  }
+  return nfb;
+}
+
+/* Inputs of one edge along k, (p, q, k) cyclic, edge at +1/2 in p and q:
+ * p-face velocity components p and q of side a (0 left, 1 right along p) at
+ * q-offsets -2..+3; face B_p at q-offsets -2..+3; face B_q at p-offsets
+ * -2..+3; p-face speeds at q-offsets 0, +1; q-face speeds at p-offsets 0, +1. */
+typedef struct {
+  double vp[2][6], vq[2][6], bp[6], bq[6];
+  double app[2], amp[2], aqp[2], aqm[2];
+} edge_in;
+
+static void rec5(const double *st, double *l, double *r) {
+  const double s[5] = {st[0], st[1], st[2], st[3], st[4]};
+  const double t[5] = {st[5], st[4], st[3], st[2], st[1]};
+  *l = orc_mp5(s);
+  *r = orc_mp5(t);
+}
+
+/* UCT edge field: corner states by MP5 along q of the p-face states, B_p
+ * along q, B_q along p, E^{ab} = v_q^{ab} B_p^b - v_p^{ab} B_q^a, edge speeds
+ * the maxima over the two adjacent faces of each direction. */
+static double edge_from(const edge_in *e) {
+  double vp[2][2], vq[2][2], bpL, bpR, bqL, bqR;
+  for (int a = 0; a < 2; ++a) {
+    rec5(e->vp[a], &vp[a][0], &vp[a][1]);
+    rec5(e->vq[a], &vq[a][0], &vq[a][1]);
+  }
+  rec5(e->bp, &bpL, &bpR);
+  rec5(e->bq, &bqL, &bqR);
+  double Eab[4];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) {
+      const double bpb = b ? bpR : bpL;
+      const double bqa = a ? bqR : bqL;
+      Eab[2 * a + b] = vq[a][b] * bpb - vp[a][b] * bqa;
+    }
+  const double axp = fmax(e->app[0], e->app[1]);
+  const double axm = fmax(e->amp[0], e->amp[1]);
+  const double ayp = fmax(e->aqp[0], e->aqp[1]);
+  const double aym = fmax(e->aqm[0], e->aqm[1]);
+  return orc_uct_formula(Eab, axp, axm, ayp, aym, bqL, bqR, bpL, bpR);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Grid operations                                                           */
 /* ------------------------------------------------------------------------ */
@@ -432,11 +522,6 @@ int orc_c2p(const orc_cfg *c, double *const *cons, double *const *bf, double *W,
   return nfail;
 }
 
-static int state_ok(const double *pr) {
-  const double v2 = pr[1] * pr[1] + pr[2] * pr[2] + pr[3] * pr[3];
-  return pr[0] > 0.0 && pr[4] > 0.0 && v2 < 1.0;
-}
-
 /* Spatial operator L(U) of the semi-discrete scheme (Sec. 3):
  *   rhs[0..4] = -sum_d (Fhat(+face) - Fhat(-face)) / dx_d   (cell centres)
  *   rhs[5+d]  = -(curl_h E)_d at the d-faces                 (face B)
@@ -463,33 +548,12 @@ int orc_rhs(const orc_cfg *c, double *const *prim, double *const *bf, double **r
       for (int j = 0; j < c->ny; ++j)
         for (int i = 0; i < c->nx; ++i) {
           const long id = ((long)k * c->ny + j) * c->nx + i;
-          const long ip = idx_shift(c, i, j, k, d, 1);
-          double prL[8], prR[8];
-          /* reconstructed: rho, vx, vy, vz, p and the two transverse B */
-          for (int n = 0; n < 8; ++n) {
-            if (n == 5 + d) continue;
-            rec_face(c, prim[n], i, j, k, d, &prL[n], &prR[n]);
-          }
-          prL[5 + d] = prR[5 + d] = bf[d][id];
-          if (!state_ok(prL)) {
-            for (int n = 0; n < 8; ++n)
-              if (n != 5 + d) prL[n] = prim[n][id];
-            ++nfb;
-          }
-          if (!state_ok(prR)) {
-            for (int n = 0; n < 8; ++n)
-              if (n != 5 + d) prR[n] = prim[n][ip];
-            ++nfb;
-          }
-          double f8[8], ap, am;
-          orc_riemann(c->riemann, c->gam, prL, prR, d, f8, &ap, &am);
-          for (int n = 0; n < 5; ++n) fh[5 * d + n][id] = f8[n];
-          apm[2 * d][id] = ap;
-          apm[2 * d + 1][id] = am;
-          for (int m = 0; m < 3; ++m) {
-            fv[6 * d + m][id] = prL[1 + m];
-            fv[6 * d + 3 + m][id] = prR[1 + m];
-          }
+          face_out fo;
+          nfb += face_solve(c, prim, bf, i, j, k, d, &fo);
+          for (int n = 0; n < 5; ++n) fh[5 * d + n][id] = fo.fhat[n];
+          apm[2 * d][id] = fo.ap;
+          apm[2 * d + 1][id] = fo.am;
+          for (int m = 0; m < 6; ++m) fv[6 * d + m][id] = fo.v[m];
         }
   }
 
@@ -503,8 +567,7 @@ int orc_rhs(const orc_cfg *c, double *const *prim, double *const *bf, double **r
   }
   if (amax) *amax = amx;
 
-  /* UCT: edge along kk, with p = kk+1, q = kk+2 (cyclic).  The p-face states
-   * are reconstructed along q; B_p (p-faces) along q; B_q (q-faces) along p. */
+  /* UCT: edge along kk, from the stored face arrays. */
   for (int kk = 0; kk < 3; ++kk) {
     const int p = (kk + 1) % 3, q = (kk + 2) % 3;
 #pragma omp parallel for schedule(static)
@@ -512,33 +575,27 @@ int orc_rhs(const orc_cfg *c, double *const *prim, double *const *bf, double **r
       for (int j = 0; j < c->ny; ++j)
         for (int i = 0; i < c->nx; ++i) {
           const long id = ((long)k * c->ny + j) * c->nx + i;
-          double vp[2][2], vq[2][2]; /* [a][b] */
-          for (int a = 0; a < 2; ++a) {
-            double l, r;
-            rec_face(c, fv[6 * p + 3 * a + p], i, j, k, q, &l, &r);
-            vp[a][0] = l;
-            vp[a][1] = r;
-            rec_face(c, fv[6 * p + 3 * a + q], i, j, k, q, &l, &r);
-            vq[a][0] = l;
-            vq[a][1] = r;
-          }
-          double bpL, bpR, bqL, bqR;
-          rec_face(c, bf[p], i, j, k, q, &bpL, &bpR);
-          rec_face(c, bf[q], i, j, k, p, &bqL, &bqR);
-          double Eab[4];
-          for (int a = 0; a < 2; ++a)
-            for (int b = 0; b < 2; ++b) {
-              const double bpb = b ? bpR : bpL;
-              const double bqa = a ? bqR : bqL;
-              Eab[2 * a + b] = vq[a][b] * bpb - vp[a][b] * bqa;
+          edge_in e;
+          for (int m = 0; m < 6; ++m) {
+            const long iq = idx_shift(c, i, j, k, q, m - 2);
+            for (int a = 0; a < 2; ++a) {
+              e.vp[a][m] = fv[6 * p + 3 * a + p][iq];
+              e.vq[a][m] = fv[6 * p + 3 * a + q][iq];
             }
+            e.bp[m] = bf[p][iq];
+            e.bq[m] = bf[q][idx_shift(c, i, j, k, p, m - 2)];
+          }
           const long idq = idx_shift(c, i, j, k, q, 1);
           const long idp = idx_shift(c, i, j, k, p, 1);
-          const double axp = fmax(apm[2 * p][id], apm[2 * p][idq]);
-          const double axm = fmax(apm[2 * p + 1][id], apm[2 * p + 1][idq]);
-          const double ayp = fmax(apm[2 * q][id], apm[2 * q][idp]);
-          const double aym = fmax(apm[2 * q + 1][id], apm[2 * q + 1][idp]);
-          ee[kk][id] = orc_uct_formula(Eab, axp, axm, ayp, aym, bqL, bqR, bpL, bpR);
+          e.app[0] = apm[2 * p][id];
+          e.app[1] = apm[2 * p][idq];
+          e.amp[0] = apm[2 * p + 1][id];
+          e.amp[1] = apm[2 * p + 1][idq];
+          e.aqp[0] = apm[2 * q][id];
+          e.aqp[1] = apm[2 * q][idp];
+          e.aqm[0] = apm[2 * q + 1][id];
+          e.aqm[1] = apm[2 * q + 1][idp];
+          ee[kk][id] = edge_from(&e);
         }
   }
 
@@ -581,6 +638,88 @@ int orc_rhs(const orc_cfg *c, double *const *prim, double *const *bf, double **r
   for (int n = 0; n < 3; ++n) {
     if (edge_out && edge_out[n]) memcpy(edge_out[n], ee[n], sizeof(double) * N);
     free(ee[n]);
+  }
+  return 0;
+}
+
+/* Coordinates of (i,j,k) shifted by off along d, periodic. */
+static void shift_cell(const orc_cfg *c, int *q, int d, int off) {
+  const int n[3] = {c->nx, c->ny, c->nz};
+  q[d] = ((q[d] + off) % n[d] + n[d]) % n[d];
+}
+
+/* Edge field along kk at the edge +1/2 in p and q of cell q0, computed from
+ * scratch (face states re-solved), with the same arithmetic as orc_rhs. */
+static double edge_at(const orc_cfg *c, double *const *prim, double *const *bf, const int *q0,
+                      int kk) {
+  const int p = (kk + 1) % 3, q = (kk + 2) % 3;
+  edge_in e;
+  for (int m = 0; m < 6; ++m) {
+    int a3[3] = {q0[0], q0[1], q0[2]};
+    shift_cell(c, a3, q, m - 2);
+    face_out fo;
+    face_solve(c, prim, bf, a3[0], a3[1], a3[2], p, &fo);
+    for (int a = 0; a < 2; ++a) {
+      e.vp[a][m] = fo.v[3 * a + p];
+      e.vq[a][m] = fo.v[3 * a + q];
+    }
+    if (m == 2) {
+      e.app[0] = fo.ap;
+      e.amp[0] = fo.am;
+    }
+    if (m == 3) {
+      e.app[1] = fo.ap;
+      e.amp[1] = fo.am;
+    }
+    e.bp[m] = bf[p][((long)a3[2] * c->ny + a3[1]) * c->nx + a3[0]];
+    int b3[3] = {q0[0], q0[1], q0[2]};
+    shift_cell(c, b3, p, m - 2);
+    e.bq[m] = bf[q][((long)b3[2] * c->ny + b3[1]) * c->nx + b3[0]];
+  }
+  for (int m = 0; m < 2; ++m) {
+    int a3[3] = {q0[0], q0[1], q0[2]};
+    shift_cell(c, a3, p, m);
+    face_out fo;
+    face_solve(c, prim, bf, a3[0], a3[1], a3[2], q, &fo);
+    e.aqp[m] = fo.ap;
+    e.aqm[m] = fo.am;
+  }
+  return edge_from(&e);
+}
+
+/* L(U) at the listed cells only (linear indices cells[0..ncells-1]), with the
+ * arithmetic of orc_rhs: out[8*s + n] for n = D, Sx, Sy, Sz, U, Bx, By, Bz
+ * (face B at the cell's +faces).  For sampled checks of large grids. */
+int orc_rhs_cells(const orc_cfg *c, double *const *prim, double *const *bf, int ncells,
+                  const long *cells, double *out) {
+  const double dxs[3] = {cell_width(c, 0), cell_width(c, 1), cell_width(c, 2)};
+#pragma omp parallel for schedule(dynamic)
+  for (int sidx = 0; sidx < ncells; ++sidx) {
+    const long id = cells[sidx];
+    const int q0[3] = {(int)(id % c->nx), (int)((id / c->nx) % c->ny),
+                       (int)(id / ((long)c->nx * c->ny))};
+    face_out fp[3], fm[3];
+    for (int d = 0; d < 3; ++d) {
+      face_solve(c, prim, bf, q0[0], q0[1], q0[2], d, &fp[d]);
+      int m3[3] = {q0[0], q0[1], q0[2]};
+      shift_cell(c, m3, d, -1);
+      face_solve(c, prim, bf, m3[0], m3[1], m3[2], d, &fm[d]);
+    }
+    for (int n = 0; n < 5; ++n) {
+      double s = 0.0;
+      for (int d = 0; d < 3; ++d) s += (fp[d].fhat[n] - fm[d].fhat[n]) / dxs[d];
+      out[8L * sidx + n] = -s;
+    }
+    for (int d = 0; d < 3; ++d) {
+      const int p = (d + 1) % 3, q = (d + 2) % 3;
+      int a3[3] = {q0[0], q0[1], q0[2]};
+      int b3[3] = {q0[0], q0[1], q0[2]};
+      shift_cell(c, a3, p, -1);
+      shift_cell(c, b3, q, -1);
+      const double dpEq = (edge_at(c, prim, bf, q0, q) - edge_at(c, prim, bf, a3, q)) / dxs[p];
+      const double dqEp = (edge_at(c, prim, bf, q0, p) - edge_at(c, prim, bf, b3, p)) / dxs[q];
+      out[8L * sidx + 5 + d] = -(dpEq - dqEp);
+    }
   }
   return 0;
 }
@@ -659,4 +798,13 @@ void orc_sums(const orc_cfg *c, double *const *cons, double *const *bf, double *
     for (long id = 0; id < N; ++id) s += a[id];
     sums[n] = s;
   }
+}
+
+/* Number of OpenMP threads the grid operations use. */
+int orc_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
 }

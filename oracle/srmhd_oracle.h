@@ -73,9 +73,12 @@ int orc_c2p(const orc_cfg *c, double *const *cons, double *const *bf,
 int orc_rhs(const orc_cfg *c, double *const *prim, double *const *bf,
             double **rhs, double *amax, double **fhat, double **apm,
             double **face_v, double **edge_e, orc_stats *st);
+int orc_rhs_cells(const orc_cfg *c, double *const *prim, double *const *bf, int ncells,
+                  const long *cells, double *out);
 int orc_step(const orc_cfg *c, double **cons, double **bf, double *W,
              int nsteps, double *t, double *dt_last, orc_stats *st);
 double orc_divb_max(const orc_cfg *c, double *const *bf);
+int orc_num_threads(void);
 void orc_sums(const orc_cfg *c, double *const *cons, double *const *bf,
               double *sums);
 

@@ -1,0 +1,211 @@
+"""ctypes binding of libsrmhd.so: the entry points of include/srmhd.h with
+the same names, argument marshalling only.  Every computation runs in the
+HIP library; if the library is missing this module raises instead of falling
+back to anything else.
+
+Pointers passed to the device-side entry points are integers (device
+addresses, e.g. ``tensor.data_ptr()``) or sequences of them.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsrmhd.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "srmhd.h")
+
+SRMHD_OK = 0
+SRMHD_E_INVAL = -1
+SRMHD_E_HIP = -2
+SRMHD_E_C2P = -3
+SRMHD_E_NONFINITE = -4
+SRMHD_E_STATE = -5
+SRMHD_HLL, SRMHD_LLF = 0, 1
+SRMHD_FP64, SRMHD_MIXED = 0, 1
+SRMHD_GUESS_PREV, SRMHD_GUESS_MLP, SRMHD_GUESS_COLD = 0, 1, 2
+ERRBIT_C2P, ERRBIT_NONFINITE, ERRBIT_DT, ERRBIT_PRESSURE = 1, 2, 4, 8
+
+
+class SrmhdError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"srmhd error {code}: {msg}")
+        self.code = code
+
+
+class Config(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
+                ("lx", C.c_double), ("ly", C.c_double), ("lz", C.c_double),
+                ("gamma_ad", C.c_double), ("cfl", C.c_double), ("dt_fixed", C.c_double),
+                ("riemann", C.c_int), ("precision", C.c_int), ("guess", C.c_int),
+                ("newton_maxit", C.c_int), ("newton_tol", C.c_double),
+                ("pfloor", C.c_double), ("collect_stats", C.c_int)]
+
+
+class Buffers(C.Structure):
+    _fields_ = [("cons", C.c_void_p * 5), ("bface", C.c_void_p * 3),
+                ("guess_w", C.c_void_p), ("work", C.c_void_p), ("work_bytes", C.c_size_t)]
+
+
+class Diag(C.Structure):
+    _fields_ = [("t", C.c_double), ("dt", C.c_double), ("step", C.c_long),
+                ("amax", C.c_double), ("divb_max", C.c_double), ("sums", C.c_double * 8),
+                ("newton_iters", C.c_long), ("newton_calls", C.c_long),
+                ("newton_hist", C.c_long * 32), ("c2p_failures", C.c_long),
+                ("recon_fallbacks", C.c_long), ("floors", C.c_long),
+                ("mlp_fallbacks", C.c_long), ("error_word", C.c_uint)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["sums"] = list(self.sums)
+        d["newton_hist"] = list(self.newton_hist)
+        return d
+
+
+_lib = None
+_VP = C.c_void_p
+_CTX = C.c_void_p
+
+
+def lib():
+    """Load libsrmhd.so (built by ``paper_2401_03008_amd.build``)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build the HIP library first "
+                "(python -c 'import __graft_entry__ as g; g.build()')")
+        L = C.CDLL(LIB_PATH)
+        L.srmhd_config_default.argtypes = [C.POINTER(Config)]
+        L.srmhd_work_bytes.argtypes = [C.POINTER(Config), C.POINTER(C.c_size_t)]
+        L.srmhd_create.argtypes = [C.POINTER(Config), C.POINTER(Buffers), _VP, C.POINTER(_CTX)]
+        L.srmhd_init_from_prims.argtypes = [_CTX, C.POINTER(_VP), C.POINTER(_VP)]
+        L.srmhd_step.argtypes = [_CTX, C.c_int]
+        L.srmhd_rhs.argtypes = [_CTX, C.POINTER(_VP), _VP]
+        L.srmhd_get_primitives.argtypes = [_CTX, C.POINTER(_VP)]
+        L.srmhd_get_diagnostics.argtypes = [_CTX, C.POINTER(Diag)]
+        L.srmhd_reset_counters.argtypes = [_CTX]
+        L.srmhd_get_time.argtypes = [_CTX, C.POINTER(C.c_double), C.POINTER(C.c_long),
+                                     C.POINTER(C.c_double)]
+        L.srmhd_set_time.argtypes = [_CTX, C.c_double, C.c_long]
+        L.srmhd_kernel_timing.argtypes = [_CTX, C.c_int]
+        L.srmhd_get_kernel_times.argtypes = [_CTX, C.POINTER(C.c_double), C.POINTER(C.c_long)]
+        L.srmhd_last_error.argtypes = [_CTX]
+        L.srmhd_last_error.restype = C.c_char_p
+        L.srmhd_strerror.argtypes = [C.c_int]
+        L.srmhd_strerror.restype = C.c_char_p
+        L.srmhd_destroy.argtypes = [_CTX]
+        L.srmhd_destroy.restype = None
+        _lib = L
+    return _lib
+
+
+def header_functions():
+    """Names of the functions declared in include/srmhd.h."""
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(srmhd_\w+)\s*\(", txt)))
+
+
+def _check(rc, ctx=None):
+    if rc != SRMHD_OK:
+        msg = lib().srmhd_last_error(ctx)
+        raise SrmhdError(rc, (msg or b"").decode() or lib().srmhd_strerror(rc).decode())
+    return rc
+
+
+def _ptrs(seq, n):
+    if len(seq) != n:
+        raise ValueError(f"expected {n} pointers, got {len(seq)}")
+    return (_VP * n)(*[int(p) for p in seq])
+
+
+# ---------------------------------------------------------------- entry points
+def srmhd_config_default():
+    cfg = Config()
+    _check(lib().srmhd_config_default(C.byref(cfg)))
+    return cfg
+
+
+def srmhd_work_bytes(cfg):
+    n = C.c_size_t()
+    _check(lib().srmhd_work_bytes(C.byref(cfg), C.byref(n)))
+    return n.value
+
+
+def srmhd_create(cfg, cons, bface, guess_w, work, work_bytes, stream=0):
+    buf = Buffers()
+    buf.cons = (_VP * 5)(*[int(p) for p in cons])
+    buf.bface = (_VP * 3)(*[int(p) for p in bface])
+    buf.guess_w = int(guess_w)
+    buf.work = int(work)
+    buf.work_bytes = int(work_bytes)
+    ctx = _CTX()
+    _check(lib().srmhd_create(C.byref(cfg), C.byref(buf), _VP(int(stream) or None), C.byref(ctx)))
+    return ctx
+
+
+def srmhd_init_from_prims(ctx, prim5, bface):
+    _check(lib().srmhd_init_from_prims(ctx, _ptrs(prim5, 5), _ptrs(bface, 3)), ctx)
+
+
+def srmhd_step(ctx, nsteps):
+    _check(lib().srmhd_step(ctx, int(nsteps)), ctx)
+
+
+def srmhd_rhs(ctx, rhs, amax_dev):
+    _check(lib().srmhd_rhs(ctx, _ptrs(rhs, 8), _VP(int(amax_dev))), ctx)
+
+
+def srmhd_get_primitives(ctx, prim):
+    _check(lib().srmhd_get_primitives(ctx, _ptrs(prim, 8)), ctx)
+
+
+def srmhd_get_diagnostics(ctx, raise_on_error=True):
+    d = Diag()
+    rc = lib().srmhd_get_diagnostics(ctx, C.byref(d))
+    if raise_on_error:
+        _check(rc, ctx)
+    return d, rc
+
+
+def srmhd_reset_counters(ctx):
+    _check(lib().srmhd_reset_counters(ctx), ctx)
+
+
+def srmhd_get_time(ctx):
+    t, st, dt = C.c_double(), C.c_long(), C.c_double()
+    _check(lib().srmhd_get_time(ctx, C.byref(t), C.byref(st), C.byref(dt)), ctx)
+    return t.value, st.value, dt.value
+
+
+def srmhd_set_time(ctx, t, step):
+    _check(lib().srmhd_set_time(ctx, float(t), int(step)), ctx)
+
+
+NKCLASS = 9
+KCLASS_NAMES = ["c2p", "flux_x", "flux_y", "flux_z", "uct_x", "uct_y", "uct_z", "update", "dt"]
+
+
+def srmhd_kernel_timing(ctx, enable):
+    _check(lib().srmhd_kernel_timing(ctx, 1 if enable else 0), ctx)
+
+
+def srmhd_get_kernel_times(ctx):
+    ms = (C.c_double * NKCLASS)()
+    n = (C.c_long * NKCLASS)()
+    _check(lib().srmhd_get_kernel_times(ctx, ms, n), ctx)
+    return {KCLASS_NAMES[k]: (ms[k], n[k]) for k in range(NKCLASS)}
+
+
+def srmhd_last_error(ctx=None):
+    return (lib().srmhd_last_error(ctx) or b"").decode()
+
+
+def srmhd_strerror(code):
+    return lib().srmhd_strerror(int(code)).decode()
+
+
+def srmhd_destroy(ctx):
+    lib().srmhd_destroy(ctx)

@@ -1,0 +1,558 @@
+// srmhd_api.hip -- the C ABI of libsrmhd (declared in include/srmhd.h):
+// configuration checks, carving of the caller's work buffer, and the launch
+// sequence of the SSP-RK3 stages.  Host code only; every launch goes to the
+// caller's stream.
+#include "srmhd.h"
+#include "srmhd_kernels.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace srmhd;
+
+struct srmhd_ctx {
+  srmhd_config cfg;
+  srmhd_buffers buf;
+  hipStream_t stream;
+  int device;
+  GridDims g;
+  long long ncell;
+  bool mixed;
+  bool initialized;
+  DevScalars* sc;
+  unsigned long long* counters;
+  double* partial;
+  double* u0[8];
+  double* prim64[8];
+  float* prim32[8];
+  void* fhat[3][5];
+  void* apm[3][2];
+  void* fv[3][6];
+  double* edge[3];
+  std::string err;
+  // per-kernel event timing
+  bool timing;
+  std::vector<hipEvent_t> ev;      // pool, pairs (start, stop)
+  std::vector<int> ev_class;       // class of each pair in flight
+  int ev_used;
+  double kms[SRMHD_NKCLASS];
+  long kcount[SRMHD_NKCLASS];
+};
+
+static std::string g_create_error;
+
+namespace {
+
+int fail(srmhd_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  else g_create_error = msg;
+  return code;
+}
+
+int hip_check(srmhd_ctx* c, hipError_t e, const char* what) {
+  if (e == hipSuccess) return SRMHD_OK;
+  return fail(c, SRMHD_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int check_launch(srmhd_ctx* c, const char* what) {
+  return hip_check(c, hipGetLastError(), what);
+}
+
+constexpr int kEventPairs = 2048;
+
+int drain_events(srmhd_ctx* c) {
+  if (c->ev_used == 0) return SRMHD_OK;
+  int rc = hip_check(c, hipStreamSynchronize(c->stream), "stream sync (timing)");
+  if (rc != SRMHD_OK) return rc;
+  for (int n = 0; n < c->ev_used; ++n) {
+    float ms = 0.f;
+    rc = hip_check(c, hipEventElapsedTime(&ms, c->ev[2 * n], c->ev[2 * n + 1]), "event time");
+    if (rc != SRMHD_OK) return rc;
+    c->kms[c->ev_class[n]] += ms;
+    c->kcount[c->ev_class[n]] += 1;
+  }
+  c->ev_used = 0;
+  return SRMHD_OK;
+}
+
+// Scoped start/stop events around one launch of class k (no-op if timing off).
+struct KTimer {
+  srmhd_ctx* c;
+  int pair;
+  KTimer(srmhd_ctx* cc, int k) : c(cc), pair(-1) {
+    if (!c->timing) return;
+    if (c->ev_used == kEventPairs) drain_events(c);
+    pair = c->ev_used++;
+    c->ev_class[pair] = k;
+    (void)hipEventRecord(c->ev[2 * pair], c->stream);
+  }
+  ~KTimer() {
+    if (pair >= 0) (void)hipEventRecord(c->ev[2 * pair + 1], c->stream);
+  }
+};
+
+std::string validate(const srmhd_config* c) {
+  if (!c) return "config is NULL";
+  if (c->nx < 8 || c->ny < 8 || c->nz < 8) return "nx, ny, nz must each be >= 8";
+  if ((long long)c->nx * c->ny * c->nz >= (1LL << 31)) return "nx*ny*nz must be < 2^31";
+  if (c->nz > 65535 || (c->ny + kBlockY - 1) / kBlockY > 65535) return "grid too tall";
+  if (!(c->lx > 0 && c->ly > 0 && c->lz > 0)) return "box lengths must be > 0";
+  if (!(c->gamma_ad > 1.0 && c->gamma_ad <= 2.0)) return "gamma_ad must be in (1, 2]";
+  if (!(c->dt_fixed > 0.0) && !(c->cfl > 0.0 && c->cfl <= 1.0))
+    return "cfl must be in (0, 1] unless dt_fixed > 0";
+  if (!(c->dt_fixed >= 0.0) || !std::isfinite(c->dt_fixed)) return "dt_fixed must be >= 0";
+  if (c->riemann != SRMHD_HLL && c->riemann != SRMHD_LLF) return "riemann must be HLL or LLF";
+  if (c->precision != SRMHD_FP64 && c->precision != SRMHD_MIXED) return "bad precision";
+  if (c->guess != SRMHD_GUESS_PREV && c->guess != SRMHD_GUESS_COLD && c->guess != SRMHD_GUESS_MLP)
+    return "bad guess mode";
+  if (c->guess == SRMHD_GUESS_MLP) return "learned guess is not available in this build";
+  if (c->newton_maxit < 1 || c->newton_maxit > 1000) return "newton_maxit must be in 1..1000";
+  if (!(c->newton_tol > 0.0 && c->newton_tol < 1e-3)) return "newton_tol must be in (0, 1e-3)";
+  if (!(c->pfloor >= 0.0 && c->pfloor < 1.0)) return "pfloor must be in [0, 1)";
+  return "";
+}
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Work layout: scalars | counters | reduce partials | arrays.
+struct Layout {
+  size_t off_sc, off_cnt, off_part, off_arr, total;
+  size_t arr_bytes64, arr_bytes32;
+  int n64, n32;  // number of FP64 / FP32 arrays
+};
+
+Layout layout_of(const srmhd_config* c) {
+  Layout L;
+  const size_t n = (size_t)c->nx * c->ny * c->nz;
+  L.off_sc = 0;
+  L.off_cnt = align_up(sizeof(DevScalars));
+  L.off_part = L.off_cnt + align_up(sizeof(unsigned long long) * kReplicas * CNT_N);
+  L.off_arr = L.off_part + align_up(sizeof(double) * 9 * 1024);
+  L.arr_bytes64 = align_up(n * sizeof(double));
+  L.arr_bytes32 = align_up(n * sizeof(float));
+  const bool mixed = c->precision == SRMHD_MIXED;
+  // U0 (8) + edge E (3) always FP64; prims FP64 (8) or FP32 (8); faces
+  // (15 fluxes + 6 speeds + 18 velocity states) in the flux precision.
+  L.n64 = 8 + 3 + (mixed ? 0 : 8 + 39);
+  L.n32 = mixed ? 8 + 39 : 0;
+  L.total = L.off_arr + L.n64 * L.arr_bytes64 + L.n32 * L.arr_bytes32;
+  return L;
+}
+
+template <typename TS>
+void stage_flux(srmhd_ctx* c, bool cfl) {
+  const bool stats = c->cfg.collect_stats != 0;
+  for (int d = 0; d < 3; ++d) {
+    FluxArgs<TS> a;
+    a.g = c->g;
+    for (int n = 0; n < 8; ++n)
+      a.prim[n] = c->mixed ? (const TS*)c->prim32[n] : (const TS*)c->prim64[n];
+    a.bn = c->buf.bface[d];
+    for (int n = 0; n < 5; ++n) a.fhat[n] = (TS*)c->fhat[d][n];
+    a.ap = (TS*)c->apm[d][0];
+    a.am = (TS*)c->apm[d][1];
+    for (int n = 0; n < 6; ++n) a.fv[n] = (TS*)c->fv[d][n];
+    const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
+    a.apm_other[0] = (const TS*)c->apm[t1][0];
+    a.apm_other[1] = (const TS*)c->apm[t1][1];
+    a.apm_other[2] = (const TS*)c->apm[t2][0];
+    a.apm_other[3] = (const TS*)c->apm[t2][1];
+    a.amax_bits = &c->sc->amax_bits;
+    a.gam = c->cfg.gamma_ad;
+    a.riemann = c->cfg.riemann;
+    a.counters = c->counters;
+    KTimer kt(c, 1 + d);
+    launch_flux<TS>(d, a, cfl && d == 2, stats, c->stream);
+  }
+}
+
+template <typename TS>
+void stage_uct_update(srmhd_ctx* c, int stage, double* const* rhs_out) {
+  for (int k = 0; k < 3; ++k) {
+    const int p = (k + 1) % 3, q = (k + 2) % 3;
+    UctArgs<TS> a;
+    a.g = c->g;
+    for (int n = 0; n < 6; ++n) a.fvp[n] = (const TS*)c->fv[p][n];
+    a.app = (const TS*)c->apm[p][0];
+    a.amp = (const TS*)c->apm[p][1];
+    a.apq = (const TS*)c->apm[q][0];
+    a.amq = (const TS*)c->apm[q][1];
+    a.bp = c->buf.bface[p];
+    a.bq = c->buf.bface[q];
+    a.e = c->edge[k];
+    KTimer kt(c, 4 + k);
+    launch_uct<TS>(k, a, c->stream);
+  }
+  UpdArgs<TS> u;
+  u.g = c->g;
+  for (int d = 0; d < 3; ++d)
+    for (int n = 0; n < 5; ++n) u.fhat[d][n] = (const TS*)c->fhat[d][n];
+  for (int k = 0; k < 3; ++k) u.e[k] = c->edge[k];
+  for (int n = 0; n < 5; ++n) u.u[n] = c->buf.cons[n];
+  for (int d = 0; d < 3; ++d) u.u[5 + d] = c->buf.bface[d];
+  for (int n = 0; n < 8; ++n) {
+    u.u0[n] = c->u0[n];
+    u.rhs_out[n] = rhs_out ? rhs_out[n] : nullptr;
+  }
+  u.sc = c->sc;
+  KTimer kt(c, 7);
+  launch_update<TS>(stage, u, c->stream);
+}
+
+void launch_c2p_into(srmhd_ctx* c, double* const* prim64, float* const* prim32, int guess) {
+  C2PArgs a;
+  a.g = c->g;
+  for (int n = 0; n < 5; ++n) a.cons[n] = c->buf.cons[n];
+  for (int d = 0; d < 3; ++d) a.bf[d] = c->buf.bface[d];
+  a.W = c->buf.guess_w;
+  for (int n = 0; n < 8; ++n) {
+    a.prim64[n] = prim64 ? prim64[n] : nullptr;
+    a.prim32[n] = prim32 ? prim32[n] : nullptr;
+  }
+  a.gam = c->cfg.gamma_ad;
+  a.tol = c->cfg.newton_tol;
+  a.pfloor = c->cfg.pfloor;
+  a.maxit = c->cfg.newton_maxit;
+  a.guess = guess;
+  a.counters = c->counters;
+  a.err = &c->sc->err;
+  KTimer kt(c, 0);
+  launch_c2p(a, c->cfg.collect_stats != 0, c->stream);
+}
+
+// One RK stage (1..3), or stage 0 = L(U) into rhs_out.
+void run_stage(srmhd_ctx* c, int stage, double* const* rhs_out) {
+  const int guess = c->cfg.guess == SRMHD_GUESS_COLD ? 2 : 0;
+  if (c->mixed)
+    launch_c2p_into(c, nullptr, c->prim32, guess);
+  else
+    launch_c2p_into(c, c->prim64, nullptr, guess);
+  const bool cfl = stage <= 1;
+  if (c->mixed) stage_flux<float>(c, cfl);
+  else stage_flux<double>(c, cfl);
+  if (stage == 1) {
+    KTimer kt(c, 8);
+    launch_dt(c->sc, c->cfg.cfl, c->cfg.dt_fixed, c->stream);
+  }
+  if (c->mixed) stage_uct_update<float>(c, stage, rhs_out);
+  else stage_uct_update<double>(c, stage, rhs_out);
+}
+
+__global__ void k_take_amax(srmhd::DevScalars* sc, double* out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    *out = __longlong_as_double((long long)sc->amax_bits);
+    sc->amax_bits = 0ull;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int srmhd_config_default(srmhd_config* cfg) {
+  if (!cfg) return SRMHD_E_INVAL;
+  std::memset(cfg, 0, sizeof(*cfg));
+  cfg->nx = cfg->ny = cfg->nz = 32;
+  cfg->lx = cfg->ly = cfg->lz = 1.0;
+  cfg->gamma_ad = 4.0 / 3.0;
+  cfg->cfl = 0.5;
+  cfg->dt_fixed = 0.0;
+  cfg->riemann = SRMHD_HLL;
+  cfg->precision = SRMHD_FP64;
+  cfg->guess = SRMHD_GUESS_PREV;
+  cfg->newton_maxit = 50;
+  cfg->newton_tol = 1e-14;
+  cfg->pfloor = 0.0;
+  cfg->collect_stats = 1;
+  return SRMHD_OK;
+}
+
+int srmhd_work_bytes(const srmhd_config* cfg, size_t* bytes) {
+  const std::string v = validate(cfg);
+  if (!v.empty()) return fail(nullptr, SRMHD_E_INVAL, v);
+  if (!bytes) return fail(nullptr, SRMHD_E_INVAL, "bytes is NULL");
+  *bytes = layout_of(cfg).total;
+  return SRMHD_OK;
+}
+
+int srmhd_create(const srmhd_config* cfg, const srmhd_buffers* buf, void* stream,
+                 srmhd_ctx** out) {
+  if (!out) return fail(nullptr, SRMHD_E_INVAL, "out is NULL");
+  *out = nullptr;
+  const std::string v = validate(cfg);
+  if (!v.empty()) return fail(nullptr, SRMHD_E_INVAL, v);
+  if (!buf) return fail(nullptr, SRMHD_E_INVAL, "buffers is NULL");
+  for (int n = 0; n < 5; ++n)
+    if (!buf->cons[n]) return fail(nullptr, SRMHD_E_INVAL, "cons pointer is NULL");
+  for (int d = 0; d < 3; ++d)
+    if (!buf->bface[d]) return fail(nullptr, SRMHD_E_INVAL, "bface pointer is NULL");
+  if (!buf->guess_w) return fail(nullptr, SRMHD_E_INVAL, "guess_w is NULL");
+  const Layout L = layout_of(cfg);
+  if (!buf->work || buf->work_bytes < L.total)
+    return fail(nullptr, SRMHD_E_INVAL, "work buffer missing or smaller than srmhd_work_bytes");
+  if (((uintptr_t)buf->work) % kAlign != 0)
+    return fail(nullptr, SRMHD_E_INVAL, "work buffer must be 256-byte aligned");
+
+  srmhd_ctx* c = new srmhd_ctx();
+  c->cfg = *cfg;
+  c->buf = *buf;
+  c->stream = (hipStream_t)stream;
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return fail(nullptr, SRMHD_E_HIP, "hipGetDevice failed");
+  }
+  c->g.nx = cfg->nx;
+  c->g.ny = cfg->ny;
+  c->g.nz = cfg->nz;
+  c->g.inv_dx[0] = cfg->nx / cfg->lx;
+  c->g.inv_dx[1] = cfg->ny / cfg->ly;
+  c->g.inv_dx[2] = cfg->nz / cfg->lz;
+  c->ncell = (long long)cfg->nx * cfg->ny * cfg->nz;
+  c->mixed = cfg->precision == SRMHD_MIXED;
+  c->initialized = false;
+  c->timing = false;
+  c->ev_used = 0;
+  for (int k = 0; k < SRMHD_NKCLASS; ++k) {
+    c->kms[k] = 0.0;
+    c->kcount[k] = 0;
+  }
+  char* w = (char*)buf->work;
+  c->sc = (DevScalars*)(w + L.off_sc);
+  c->counters = (unsigned long long*)(w + L.off_cnt);
+  c->partial = (double*)(w + L.off_part);
+  char* p = w + L.off_arr;
+  auto take64 = [&]() { double* r = (double*)p; p += L.arr_bytes64; return r; };
+  auto take32 = [&]() { float* r = (float*)p; p += L.arr_bytes32; return r; };
+  auto takeT = [&]() -> void* { return c->mixed ? (void*)take32() : (void*)take64(); };
+  for (int n = 0; n < 8; ++n) c->u0[n] = take64();
+  for (int k = 0; k < 3; ++k) c->edge[k] = take64();
+  for (int n = 0; n < 8; ++n) {
+    c->prim64[n] = c->mixed ? nullptr : take64();
+    c->prim32[n] = c->mixed ? take32() : nullptr;
+  }
+  for (int d = 0; d < 3; ++d) {
+    for (int n = 0; n < 5; ++n) c->fhat[d][n] = takeT();
+    for (int n = 0; n < 2; ++n) c->apm[d][n] = takeT();
+    for (int n = 0; n < 6; ++n) c->fv[d][n] = takeT();
+  }
+  // clear scalars and counters (a fill kernel, no memset node)
+  launch_zero_u64((unsigned long long*)w, L.off_part / sizeof(unsigned long long), c->stream);
+  const int rc = check_launch(c, "clearing work scalars");
+  if (rc != SRMHD_OK) {
+    g_create_error = c->err;
+    delete c;
+    return rc;
+  }
+  *out = c;
+  return SRMHD_OK;
+}
+
+int srmhd_init_from_prims(srmhd_ctx* c, const double* const prim5[5], const double* const bface[3]) {
+  if (!c) return SRMHD_E_INVAL;
+  if (!prim5 || !bface) return fail(c, SRMHD_E_INVAL, "prim5/bface is NULL");
+  for (int n = 0; n < 5; ++n)
+    if (!prim5[n]) return fail(c, SRMHD_E_INVAL, "prim5 entry is NULL");
+  for (int d = 0; d < 3; ++d)
+    if (!bface[d]) return fail(c, SRMHD_E_INVAL, "bface entry is NULL");
+  InitArgs a;
+  a.g = c->g;
+  for (int n = 0; n < 5; ++n) {
+    a.prim5[n] = prim5[n];
+    a.cons[n] = c->buf.cons[n];
+  }
+  for (int d = 0; d < 3; ++d) {
+    a.bf_in[d] = bface[d];
+    a.bf[d] = c->buf.bface[d];
+  }
+  a.W = c->buf.guess_w;
+  a.gam = c->cfg.gamma_ad;
+  // state arrays may alias the inputs only for bface (copied in place)
+  launch_init(a, c->stream);
+  const Layout L = layout_of(&c->cfg);
+  launch_zero_u64((unsigned long long*)c->buf.work, L.off_part / sizeof(unsigned long long),
+                  c->stream);
+  const int rc = check_launch(c, "init_from_prims");
+  if (rc == SRMHD_OK) c->initialized = true;
+  return rc;
+}
+
+int srmhd_step(srmhd_ctx* c, int nsteps) {
+  if (!c) return SRMHD_E_INVAL;
+  if (!c->initialized) return fail(c, SRMHD_E_STATE, "step before init_from_prims");
+  if (nsteps < 0) return fail(c, SRMHD_E_INVAL, "nsteps < 0");
+  for (int s = 0; s < nsteps; ++s) {
+    run_stage(c, 1, nullptr);
+    run_stage(c, 2, nullptr);
+    run_stage(c, 3, nullptr);
+  }
+  return check_launch(c, "step");
+}
+
+int srmhd_rhs(srmhd_ctx* c, double* const rhs[8], double* amax_dev) {
+  if (!c) return SRMHD_E_INVAL;
+  if (!c->initialized) return fail(c, SRMHD_E_STATE, "rhs before init_from_prims");
+  if (!rhs || !amax_dev) return fail(c, SRMHD_E_INVAL, "rhs/amax is NULL");
+  for (int n = 0; n < 8; ++n)
+    if (!rhs[n]) return fail(c, SRMHD_E_INVAL, "rhs entry is NULL");
+  // the running CFL maximum belongs to the step sequence: clear, use, clear
+  hipLaunchKernelGGL(k_take_amax, dim3(1), dim3(64), 0, c->stream, c->sc, amax_dev);
+  run_stage(c, 0, rhs);
+  hipLaunchKernelGGL(k_take_amax, dim3(1), dim3(64), 0, c->stream, c->sc, amax_dev);
+  return check_launch(c, "rhs");
+}
+
+int srmhd_get_primitives(srmhd_ctx* c, double* const prim[8]) {
+  if (!c) return SRMHD_E_INVAL;
+  if (!c->initialized) return fail(c, SRMHD_E_STATE, "get_primitives before init_from_prims");
+  if (!prim) return fail(c, SRMHD_E_INVAL, "prim is NULL");
+  for (int n = 0; n < 8; ++n)
+    if (!prim[n]) return fail(c, SRMHD_E_INVAL, "prim entry is NULL");
+  launch_c2p_into(c, prim, nullptr, c->cfg.guess == SRMHD_GUESS_COLD ? 2 : 0);
+  return check_launch(c, "get_primitives");
+}
+
+int srmhd_get_diagnostics(srmhd_ctx* c, srmhd_diag* out) {
+  if (!c) return SRMHD_E_INVAL;
+  if (!out) return fail(c, SRMHD_E_INVAL, "out is NULL");
+  std::memset(out, 0, sizeof(*out));
+  if (c->initialized) {
+    ReduceArgs a;
+    a.g = c->g;
+    for (int n = 0; n < 5; ++n) a.a[n] = c->buf.cons[n];
+    for (int d = 0; d < 3; ++d) {
+      a.a[5 + d] = c->buf.bface[d];
+      a.bf[d] = c->buf.bface[d];
+    }
+    a.partial = c->partial;
+    a.nblocks = reduce_blocks(c->g);
+    a.sc = c->sc;
+    launch_reduce(a, c->stream);
+    int rc = check_launch(c, "diagnostics reduction");
+    if (rc != SRMHD_OK) return rc;
+  }
+  DevScalars sc;
+  std::vector<unsigned long long> cnt((size_t)kReplicas * CNT_N);
+  int rc = hip_check(c, hipMemcpyAsync(&sc, c->sc, sizeof(sc), hipMemcpyDeviceToHost, c->stream),
+                     "copy scalars");
+  if (rc != SRMHD_OK) return rc;
+  rc = hip_check(c, hipMemcpyAsync(cnt.data(), c->counters, cnt.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, c->stream),
+                 "copy counters");
+  if (rc != SRMHD_OK) return rc;
+  rc = hip_check(c, hipStreamSynchronize(c->stream), "stream sync");
+  if (rc != SRMHD_OK) return rc;
+  unsigned long long tot[CNT_N] = {0};
+  for (int r = 0; r < kReplicas; ++r)
+    for (int n = 0; n < CNT_N; ++n) tot[n] += cnt[r * CNT_N + n];
+  out->t = sc.t;
+  out->dt = sc.dt;
+  out->step = (long)sc.step;
+  out->amax = sc.amax_last;
+  for (int n = 0; n < 8; ++n) out->sums[n] = sc.reduce_out[n];
+  out->divb_max = sc.reduce_out[8];
+  out->newton_iters = (long)tot[CNT_ITERS];
+  out->newton_calls = (long)tot[CNT_CALLS];
+  for (int b = 0; b < 32; ++b) out->newton_hist[b] = (long)tot[CNT_HIST0 + b];
+  out->c2p_failures = (long)tot[CNT_FAIL];
+  out->recon_fallbacks = (long)tot[CNT_FALLBACK];
+  out->floors = (long)tot[CNT_FLOOR];
+  out->mlp_fallbacks = (long)tot[CNT_MLPFB];
+  out->error_word = sc.err;
+  if (sc.err & (SRMHD_ERRBIT_NONFINITE | SRMHD_ERRBIT_DT))
+    return fail(c, SRMHD_E_NONFINITE, "non-finite conserved data or timestep on the device");
+  if (sc.err & (SRMHD_ERRBIT_C2P | SRMHD_ERRBIT_PRESSURE))
+    return fail(c, SRMHD_E_C2P, "Newton inversion failed in some cell");
+  return SRMHD_OK;
+}
+
+int srmhd_reset_counters(srmhd_ctx* c) {
+  if (!c) return SRMHD_E_INVAL;
+  launch_zero_u64(c->counters, (size_t)kReplicas * CNT_N, c->stream);
+  // the error word (and its padding) lives in the scalars block: clear only
+  // that 8-byte word, keeping t, dt and step
+  launch_zero_u64((unsigned long long*)&c->sc->err, 1, c->stream);
+  return check_launch(c, "reset_counters");
+}
+
+int srmhd_get_time(srmhd_ctx* c, double* t, long* step, double* dt) {
+  if (!c) return SRMHD_E_INVAL;
+  DevScalars sc;
+  int rc = hip_check(c, hipMemcpyAsync(&sc, c->sc, sizeof(sc), hipMemcpyDeviceToHost, c->stream),
+                     "copy scalars");
+  if (rc != SRMHD_OK) return rc;
+  rc = hip_check(c, hipStreamSynchronize(c->stream), "stream sync");
+  if (rc != SRMHD_OK) return rc;
+  if (t) *t = sc.t;
+  if (step) *step = (long)sc.step;
+  if (dt) *dt = sc.dt;
+  return SRMHD_OK;
+}
+
+int srmhd_set_time(srmhd_ctx* c, double t, long step) {
+  if (!c) return SRMHD_E_INVAL;
+  if (!std::isfinite(t) || step < 0) return fail(c, SRMHD_E_INVAL, "bad time or step");
+  launch_set_time(c->sc, t, step, c->stream);
+  return check_launch(c, "set_time");
+}
+
+int srmhd_kernel_timing(srmhd_ctx* c, int enable) {
+  if (!c) return SRMHD_E_INVAL;
+  int rc = drain_events(c);
+  if (rc != SRMHD_OK) return rc;
+  if (enable && c->ev.empty()) {
+    c->ev.resize(2 * kEventPairs);
+    c->ev_class.resize(kEventPairs);
+    for (auto& e : c->ev) {
+      rc = hip_check(c, hipEventCreate(&e), "hipEventCreate");
+      if (rc != SRMHD_OK) return rc;
+    }
+  }
+  c->timing = enable != 0;
+  for (int k = 0; k < SRMHD_NKCLASS; ++k) {
+    c->kms[k] = 0.0;
+    c->kcount[k] = 0;
+  }
+  return SRMHD_OK;
+}
+
+int srmhd_get_kernel_times(srmhd_ctx* c, double* ms, long* launches) {
+  if (!c) return SRMHD_E_INVAL;
+  if (!ms || !launches) return fail(c, SRMHD_E_INVAL, "ms/launches is NULL");
+  const int rc = drain_events(c);
+  if (rc != SRMHD_OK) return rc;
+  for (int k = 0; k < SRMHD_NKCLASS; ++k) {
+    ms[k] = c->kms[k];
+    launches[k] = c->kcount[k];
+  }
+  return SRMHD_OK;
+}
+
+const char* srmhd_last_error(const srmhd_ctx* c) {
+  return c ? c->err.c_str() : g_create_error.c_str();
+}
+
+const char* srmhd_strerror(int code) {
+  switch (code) {
+    case SRMHD_OK: return "ok";
+    case SRMHD_E_INVAL: return "invalid argument or configuration";
+    case SRMHD_E_HIP: return "HIP runtime error";
+    case SRMHD_E_C2P: return "Newton inversion failed";
+    case SRMHD_E_NONFINITE: return "non-finite data";
+    case SRMHD_E_STATE: return "call out of order";
+    default: return "unknown error";
+  }
+}
+
+void srmhd_destroy(srmhd_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,636 @@
+// srmhd_kernels.hip -- HIP kernels (gfx950) of one SSP-RK3 stage of 3D ideal
+// SRMHD on a periodic box, following the substep structure of Sec. 3 of
+// arXiv 2401.03008: INT + Newton inversion, REC + upwind face fluxes with
+// stored fast speeds, UCT edge fields, DER (flux divergence and curl) fused
+// with the Runge-Kutta update, and the once-per-step global speed maximum.
+//
+// Layout: structure of arrays, x fastest; a workgroup is 4 wavefronts, each
+// covering 64 consecutive x cells of one (y, z) row, so every global access of
+// a wavefront is a contiguous 512-byte (FP64) or 256-byte (FP32) segment.
+// Periodic wrap replaces ghost cells.
+#include "srmhd_kernels.hpp"
+#include "srmhd_phys.hpp"
+
+#include <float.h>
+
+namespace srmhd {
+
+constexpr unsigned kErrC2P = 1u, kErrNonfinite = 2u, kErrDt = 4u, kErrPressure = 8u;
+
+// --------------------------------------------------------------- helpers
+struct Cell {
+  int i, j, k, id;
+  bool valid;
+};
+
+__device__ __forceinline__ Cell cell_of(const GridDims& g) {
+  Cell c;
+  c.i = blockIdx.x * kBlockX + threadIdx.x;
+  c.j = blockIdx.y * kBlockY + threadIdx.y;
+  c.k = blockIdx.z;
+  c.valid = c.i < g.nx && c.j < g.ny;
+  c.id = (c.k * g.ny + c.j) * g.nx + c.i;
+  return c;
+}
+
+__device__ __forceinline__ int block_linear() {
+  return (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+}
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x; }
+
+// Stencil indices along direction dir at offsets -2..+3 (periodic).
+__device__ __forceinline__ void stencil6(const GridDims& g, const Cell& c, int dir, int* idx) {
+  const int n = dir == 0 ? g.nx : (dir == 1 ? g.ny : g.nz);
+  const int co = dir == 0 ? c.i : (dir == 1 ? c.j : c.k);
+  const int stride = dir == 0 ? 1 : (dir == 1 ? g.nx : g.nx * g.ny);
+  const int base = c.id - co * stride;
+#pragma unroll
+  for (int m = 0; m < 6; ++m) {
+    int cm = co + m - 2;
+    cm += cm < 0 ? n : 0;
+    cm -= cm >= n ? n : 0;
+    idx[m] = base + cm * stride;
+  }
+}
+
+// Index of the neighbour at offset -1 along dir (periodic).
+__device__ __forceinline__ int minus1(const GridDims& g, const Cell& c, int dir) {
+  if (dir == 0) return c.i == 0 ? c.id + g.nx - 1 : c.id - 1;
+  if (dir == 1) return c.j == 0 ? c.id + (g.ny - 1) * g.nx : c.id - g.nx;
+  return c.k == 0 ? c.id + (g.nz - 1) * g.nx * g.ny : c.id - g.nx * g.ny;
+}
+
+__device__ __forceinline__ int plus1(const GridDims& g, const Cell& c, int dir) {
+  if (dir == 0) return c.i == g.nx - 1 ? c.id - (g.nx - 1) : c.id + 1;
+  if (dir == 1) return c.j == g.ny - 1 ? c.id - (g.ny - 1) * g.nx : c.id + g.nx;
+  return c.k == g.nz - 1 ? c.id - (g.nz - 1) * g.nx * g.ny : c.id + g.nx * g.ny;
+}
+
+__device__ __forceinline__ unsigned wave_sum_u32(unsigned v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+__device__ __forceinline__ double wave_max_f64(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  return v;
+}
+
+// Per-workgroup counters in LDS, flushed with one global atomic per nonzero
+// entry into replica (workgroup mod kReplicas).
+struct BlockCounters {
+  unsigned* s;
+  __device__ void init(unsigned* sm) {
+    s = sm;
+    const int tid = threadIdx.y * kBlockX + threadIdx.x;
+    if (tid < CNT_N) s[tid] = 0;
+    __syncthreads();
+  }
+  // add `v` (per lane) to counter slot `slot` (uniform), one LDS atomic per wave
+  __device__ void add_uniform(int slot, unsigned v) {
+    const unsigned w = wave_sum_u32(v);
+    if (lane_id() == 0 && w) atomicAdd(&s[slot], w);
+  }
+  // histogram: add 1 to slot base + bin(lane) for lanes with has = true
+  __device__ void add_hist(int base, bool has, int bin) {
+    unsigned long long pending = __ballot(has);
+    while (pending) {
+      const int leader = __ffsll((long long)pending) - 1;
+      const int b = __shfl(bin, leader);
+      const unsigned long long same = __ballot(has && bin == b);
+      if (lane_id() == leader) atomicAdd(&s[base + b], (unsigned)__popcll(same));
+      pending &= ~same;
+    }
+  }
+  __device__ void flush(unsigned long long* global) {
+    __syncthreads();
+    const int tid = threadIdx.y * kBlockX + threadIdx.x;
+    if (tid < CNT_N && s[tid])
+      atomicAdd(&global[(block_linear() % kReplicas) * CNT_N + tid], (unsigned long long)s[tid]);
+  }
+};
+
+// ----------------------------------------------------------------- init
+__global__ __launch_bounds__(kThreads) void k_init(InitArgs a) {
+  const Cell c = cell_of(a.g);
+  if (!c.valid) return;
+  double bc[3];
+  for (int d = 0; d < 3; ++d) {
+    const double bp = a.bf_in[d][c.id];
+    const double bm = a.bf_in[d][minus1(a.g, c, d)];
+    bc[d] = 0.5 * (bm + bp);
+  }
+  FaceState<double> s{a.prim5[0][c.id], a.prim5[1][c.id], a.prim5[2][c.id], a.prim5[3][c.id],
+                      a.prim5[4][c.id], bc[0], bc[1], bc[2]};
+  FaceEval<double> e;
+  const double g1 = a.gam / (a.gam - 1.0);
+  face_eval(s, a.gam, g1, e);
+  for (int n = 0; n < 5; ++n) a.cons[n][c.id] = e.u[n];
+  const double v2 = s.vn * s.vn + s.vt1 * s.vt1 + s.vt2 * s.vt2;
+  a.W[c.id] = (s.rho + g1 * s.p) / (1.0 - v2);
+  for (int d = 0; d < 3; ++d) a.bf[d][c.id] = a.bf_in[d][c.id];
+}
+
+void launch_init(const InitArgs& a, hipStream_t s) {
+  dim3 grid((a.g.nx + kBlockX - 1) / kBlockX, (a.g.ny + kBlockY - 1) / kBlockY, a.g.nz);
+  hipLaunchKernelGGL(k_init, grid, dim3(kBlockX, kBlockY), 0, s, a);
+}
+
+// ------------------------------------------------------- Newton inversion
+// One-unknown Newton iteration in W = rho h Gamma^2 (the paper's first step
+// of a substep, Sec. 3).  v^2(W) = [S^2 + tau^2 (2W + B^2)/W^2]/(W + B^2)^2,
+// p(W) = (g-1)/g [W (1 - v^2) - D sqrt(1 - v^2)],
+// f(W) = W - p + B^2 (1 + v^2)/2 - tau^2/(2 W^2) - U, tau = S.B.
+// A guess with W <= 0 or v^2 >= 1 is replaced by U, doubled until usable; an
+// iterate leaving that set is halved back toward the previous one; the step
+// test is |dW| <= max(tol W, 8 eps fs/|f'|) with fs the sum of |terms| of f.
+struct C2PIn {
+  double D, U, S2, B2, tau2, gf;
+};
+
+__device__ __forceinline__ double c2p_v2(const C2PIn& q, double W) {
+  const double WB = W + q.B2;
+  return (q.S2 + q.tau2 * (2.0 * W + q.B2) / (W * W)) / (WB * WB);
+}
+
+__device__ __forceinline__ bool c2p_usable(const C2PIn& q, double W) {
+  return W > 0.0 && c2p_v2(q, W) < 1.0;
+}
+
+// returns 0 converged, 1 maxit reached, 2 unusable input, 3 p <= 0 (no floor)
+__device__ int con2prim(const double* u, double bx, double by, double bz, double gam,
+                        double& Wio, int maxit, double tol, double pfloor, double* pr,
+                        int& iters, bool& floored) {
+  iters = 0;
+  floored = false;
+  bool finite = true;
+  for (int n = 0; n < 5; ++n) finite = finite && isfinite(u[n]);
+  finite = finite && isfinite(bx) && isfinite(by) && isfinite(bz);
+  C2PIn q;
+  q.D = u[0];
+  q.U = u[4];
+  q.S2 = u[1] * u[1] + u[2] * u[2] + u[3] * u[3];
+  q.B2 = bx * bx + by * by + bz * bz;
+  const double tau = u[1] * bx + u[2] * by + u[3] * bz;
+  q.tau2 = tau * tau;
+  q.gf = (gam - 1.0) / gam;
+  if (!finite || !(q.D > 0.0) || !(q.U > 0.0)) return 2;
+
+  double w = Wio;
+  if (!(isfinite(w) && c2p_usable(q, w))) {
+    w = q.U;
+    for (int n = 0; n < 200 && !c2p_usable(q, w); ++n) w *= 2.0;
+  }
+  int it = 0;
+  bool conv = false;
+  while (it < maxit) {
+    ++it;
+    const double v2 = c2p_v2(q, w);
+    const double sqv = sqrt(1.0 - v2);
+    const double p = q.gf * (w * (1.0 - v2) - q.D * sqv);
+    const double iw = 1.0 / w;
+    const double tb = 0.5 * q.B2 * (1.0 + v2);
+    const double tt = 0.5 * q.tau2 * iw * iw;
+    const double f = w - p + tb - tt - q.U;
+    const double fs = w + fabs(p) + tb + tt + q.U;
+    const double iwb = 1.0 / (w + q.B2);
+    const double dv2 = -2.0 * q.tau2 * iw * iw * iw * iwb - 2.0 * v2 * iwb;
+    const double dp = q.gf * ((1.0 - v2) - w * dv2 + 0.5 * q.D * dv2 / sqv);
+    const double fp = 1.0 - dp + 0.5 * q.B2 * dv2 + q.tau2 * iw * iw * iw;
+    double wn = w - f / fp;
+    for (int n = 0; n < 100 && !(isfinite(wn) && c2p_usable(q, wn)); ++n) wn = 0.5 * (wn + w);
+    if (!isfinite(wn)) wn = w;
+    const double dw = wn - w;
+    w = wn;
+    if (fabs(dw) <= fmax(tol * w, 8.0 * DBL_EPSILON * fs / fabs(fp))) {
+      conv = true;
+      break;
+    }
+  }
+  Wio = w;
+  iters = it;
+  const double v2 = c2p_v2(q, w);
+  const double sqv = sqrt(1.0 - v2);
+  const double aa = tau / w, den = 1.0 / (w + q.B2);
+  pr[0] = q.D * sqv;
+  pr[1] = (u[1] + aa * bx) * den;
+  pr[2] = (u[2] + aa * by) * den;
+  pr[3] = (u[3] + aa * bz) * den;
+  pr[4] = q.gf * (w * (1.0 - v2) - q.D * sqv);
+  if (pfloor > 0.0 && pr[4] < pfloor * pr[0]) {
+    pr[4] = pfloor * pr[0];
+    floored = true;
+  }
+  if (!conv) return 1;
+  if (!(pr[4] > 0.0)) return 3;
+  return 0;
+}
+
+template <bool STATS>
+__global__ __launch_bounds__(kThreads) void k_c2p(C2PArgs a) {
+  __shared__ unsigned s_cnt[CNT_N];
+  BlockCounters bc;
+  if (STATS) bc.init(s_cnt);
+  const Cell c = cell_of(a.g);
+  int iters = 0, rc = 0;
+  bool floored = false;
+  if (c.valid) {
+    double u[5];
+    for (int n = 0; n < 5; ++n) u[n] = a.cons[n][c.id];
+    double b[3];
+    for (int d = 0; d < 3; ++d) b[d] = 0.5 * (a.bf[d][minus1(a.g, c, d)] + a.bf[d][c.id]);
+    double W = a.guess == 2 ? -1.0 : a.W[c.id];
+    double pr[5];
+    rc = con2prim(u, b[0], b[1], b[2], a.gam, W, a.maxit, a.tol, a.pfloor, pr, iters, floored);
+    a.W[c.id] = W;
+    if (a.prim64[0]) {
+      for (int n = 0; n < 5; ++n) a.prim64[n][c.id] = pr[n];
+      for (int d = 0; d < 3; ++d) a.prim64[5 + d][c.id] = b[d];
+    }
+    if (a.prim32[0]) {
+      for (int n = 0; n < 5; ++n) a.prim32[n][c.id] = (float)pr[n];
+      for (int d = 0; d < 3; ++d) a.prim32[5 + d][c.id] = (float)b[d];
+    }
+    if (rc != 0) {
+      const unsigned bit = rc == 1 ? kErrC2P : (rc == 2 ? kErrNonfinite : kErrPressure);
+      atomicOr(a.err, bit);
+    }
+  }
+  if (STATS) {
+    bc.add_uniform(CNT_ITERS, c.valid ? (unsigned)iters : 0u);
+    bc.add_uniform(CNT_CALLS, c.valid ? 1u : 0u);
+    bc.add_uniform(CNT_FAIL, (c.valid && rc != 0) ? 1u : 0u);
+    bc.add_uniform(CNT_FLOOR, (c.valid && floored) ? 1u : 0u);
+    bc.add_hist(CNT_HIST0, c.valid, iters < 31 ? iters : 31);
+    bc.flush(a.counters);
+  }
+}
+
+void launch_c2p(const C2PArgs& a, bool stats, hipStream_t s) {
+  dim3 grid((a.g.nx + kBlockX - 1) / kBlockX, (a.g.ny + kBlockY - 1) / kBlockY, a.g.nz);
+  if (stats)
+    hipLaunchKernelGGL(k_c2p<true>, grid, dim3(kBlockX, kBlockY), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_c2p<false>, grid, dim3(kBlockX, kBlockY), 0, s, a);
+}
+
+// ------------------------------------------------ REC + face physics + HLL
+// One thread per +face along DIR.  MP5 left/right states of rho, v, p and the
+// two transverse centred B; the normal B is the staggered face value.  A face
+// state with rho <= 0, p <= 0 or v^2 >= 1 is replaced by its cell's values
+// (first order) and counted.  HLL: a+ = max(0, l+_L, l+_R), a- = max(0, -l-_L,
+// -l-_R), Fhat = (a+ F_L + a- F_R - a+ a- (U_R - U_L))/(a+ + a-); LLF: a+ =
+// a- = max |l|.  Outputs the 5 fluid fluxes, a+-, and both velocity states
+// (for UCT).  With CFL, also the workgroup max of sum_d max(a+,a-)_d/dx_d
+// (needs the other two directions' speeds already stored).
+template <int DIR, typename TS, bool CFL, bool STATS>
+__global__ __launch_bounds__(kThreads) void k_flux(FluxArgs<TS> a) {
+  using T = TS;
+  constexpr int T1 = (DIR + 1) % 3, T2 = (DIR + 2) % 3;
+  __shared__ unsigned s_cnt[CNT_N];
+  __shared__ double s_max[kBlockY];
+  BlockCounters bc;
+  if (STATS) bc.init(s_cnt);
+  const Cell c = cell_of(a.g);
+  int nfb = 0;
+  double cfl_sum = 0.0;
+  if (c.valid) {
+    int idx[6];
+    stencil6(a.g, c, DIR, idx);
+    FaceState<T> L, R;
+    auto rec = [&](const TS* q, T& l, T& r) {
+      const T s0 = q[idx[0]], s1 = q[idx[1]], s2 = q[idx[2]], s3 = q[idx[3]], s4 = q[idx[4]],
+              s5 = q[idx[5]];
+      l = mp5<T>(s0, s1, s2, s3, s4);
+      r = mp5<T>(s5, s4, s3, s2, s1);
+    };
+    rec(a.prim[0], L.rho, R.rho);
+    rec(a.prim[1 + DIR], L.vn, R.vn);
+    rec(a.prim[1 + T1], L.vt1, R.vt1);
+    rec(a.prim[1 + T2], L.vt2, R.vt2);
+    rec(a.prim[4], L.p, R.p);
+    rec(a.prim[5 + T1], L.bt1, R.bt1);
+    rec(a.prim[5 + T2], L.bt2, R.bt2);
+    const T bn = (T)a.bn[c.id];
+    L.bn = R.bn = bn;
+    if (!face_state_ok(L)) {
+      const int m = idx[2];
+      L = FaceState<T>{a.prim[0][m], a.prim[1 + DIR][m], a.prim[1 + T1][m], a.prim[1 + T2][m],
+                       a.prim[4][m], bn, a.prim[5 + T1][m], a.prim[5 + T2][m]};
+      ++nfb;
+    }
+    if (!face_state_ok(R)) {
+      const int m = idx[3];
+      R = FaceState<T>{a.prim[0][m], a.prim[1 + DIR][m], a.prim[1 + T1][m], a.prim[1 + T2][m],
+                       a.prim[4][m], bn, a.prim[5 + T1][m], a.prim[5 + T2][m]};
+      ++nfb;
+    }
+    const T g = (T)a.gam, g1 = (T)(a.gam / (a.gam - 1.0));
+    FaceEval<T> eL, eR;
+    face_eval(L, g, g1, eL);
+    face_eval(R, g, g1, eR);
+    T ap, am;
+    if (a.riemann == 1) {
+      ap = fmax(fmax(fabs(eL.lm), fabs(eL.lp)), fmax(fabs(eR.lm), fabs(eR.lp)));
+      am = ap;
+    } else {
+      ap = fmax(T(0), fmax(eL.lp, eR.lp));
+      am = fmax(T(0), fmax(-eL.lm, -eR.lm));
+    }
+    const T sum = ap + am;
+    T F[5];
+    if (sum > T(0)) {
+      const T inv = T(1) / sum, apam = ap * am;
+#pragma unroll
+      for (int n = 0; n < 5; ++n) F[n] = (ap * eL.f[n] + am * eR.f[n] - apam * (eR.u[n] - eL.u[n])) * inv;
+    } else {
+#pragma unroll
+      for (int n = 0; n < 5; ++n) F[n] = T(0.5) * (eL.f[n] + eR.f[n]);
+    }
+    a.fhat[0][c.id] = F[0];
+    a.fhat[1 + DIR][c.id] = F[1];
+    a.fhat[1 + T1][c.id] = F[2];
+    a.fhat[1 + T2][c.id] = F[3];
+    a.fhat[4][c.id] = F[4];
+    a.ap[c.id] = ap;
+    a.am[c.id] = am;
+    a.fv[DIR][c.id] = L.vn;
+    a.fv[T1][c.id] = L.vt1;
+    a.fv[T2][c.id] = L.vt2;
+    a.fv[3 + DIR][c.id] = R.vn;
+    a.fv[3 + T1][c.id] = R.vt1;
+    a.fv[3 + T2][c.id] = R.vt2;
+    if (CFL) {
+      // sum over d = 0, 1, 2 in that order; the other directions' speeds are
+      // apm_other = {a+_T1, a-_T1, a+_T2, a-_T2}
+      double m[3];
+      m[DIR] = (double)fmax(ap, am);
+      m[T1] = (double)fmax(a.apm_other[0][c.id], a.apm_other[1][c.id]);
+      m[T2] = (double)fmax(a.apm_other[2][c.id], a.apm_other[3][c.id]);
+      cfl_sum = m[0] * a.g.inv_dx[0] + m[1] * a.g.inv_dx[1] + m[2] * a.g.inv_dx[2];
+    }
+  }
+  if (CFL) {
+    const double w = wave_max_f64(cfl_sum);
+    if (lane_id() == 0) s_max[threadIdx.y] = w;
+    __syncthreads();
+    if (threadIdx.x == 0 && threadIdx.y == 0) {
+      double b = s_max[0];
+      for (int n = 1; n < kBlockY; ++n) b = fmax(b, s_max[n]);
+      // +double bit patterns order like unsigned integers; NaN sorts above inf
+      atomicMax(a.amax_bits, (unsigned long long)__double_as_longlong(b));
+    }
+  }
+  if (STATS) {
+    bc.add_uniform(CNT_FALLBACK, (unsigned)nfb);
+    bc.flush(a.counters);
+  }
+}
+
+template <typename TS>
+void launch_flux(int dir, const FluxArgs<TS>& a, bool cfl, bool stats, hipStream_t s) {
+  dim3 grid((a.g.nx + kBlockX - 1) / kBlockX, (a.g.ny + kBlockY - 1) / kBlockY, a.g.nz);
+  dim3 blk(kBlockX, kBlockY);
+#define SRMHD_FLUX(D, C, S) hipLaunchKernelGGL((k_flux<D, TS, C, S>), grid, blk, 0, s, a)
+  if (dir == 0) {
+    if (stats) SRMHD_FLUX(0, false, true); else SRMHD_FLUX(0, false, false);
+  } else if (dir == 1) {
+    if (stats) SRMHD_FLUX(1, false, true); else SRMHD_FLUX(1, false, false);
+  } else {
+    if (cfl) {
+      if (stats) SRMHD_FLUX(2, true, true); else SRMHD_FLUX(2, true, false);
+    } else {
+      if (stats) SRMHD_FLUX(2, false, true); else SRMHD_FLUX(2, false, false);
+    }
+  }
+#undef SRMHD_FLUX
+}
+template void launch_flux<double>(int, const FluxArgs<double>&, bool, bool, hipStream_t);
+template void launch_flux<float>(int, const FluxArgs<float>&, bool, bool, hipStream_t);
+
+// ------------------------------------------------------------------- UCT
+// Edge field E_K at (+1/2 along P, +1/2 along Q), (P, Q, K) cyclic, in FP64:
+// the two P-face velocity states (left/right along P) are MP5-reconstructed
+// along Q to the edge (corner states ab), B_P (P faces) along Q, B_Q (Q faces)
+// along P; E^{ab} = v_Q^{ab} B_P^b - v_P^{ab} B_Q^a (E = -v x B); edge speeds
+// are the maxima over the two adjacent faces of each direction.
+template <int K, typename TS>
+__global__ __launch_bounds__(kThreads) void k_uct(UctArgs<TS> a) {
+  constexpr int P = (K + 1) % 3, Q = (K + 2) % 3;
+  const Cell c = cell_of(a.g);
+  if (!c.valid) return;
+  int iq[6], ip[6];
+  stencil6(a.g, c, Q, iq);
+  stencil6(a.g, c, P, ip);
+  auto rec = [&](auto q, const int* idx, double& l, double& r) {
+    const double s0 = (double)q[idx[0]], s1 = (double)q[idx[1]], s2 = (double)q[idx[2]],
+                 s3 = (double)q[idx[3]], s4 = (double)q[idx[4]], s5 = (double)q[idx[5]];
+    l = mp5<double>(s0, s1, s2, s3, s4);
+    r = mp5<double>(s5, s4, s3, s2, s1);
+  };
+  double vp[2][2], vq[2][2];
+#pragma unroll
+  for (int sd = 0; sd < 2; ++sd) {
+    rec(a.fvp[3 * sd + P], iq, vp[sd][0], vp[sd][1]);
+    rec(a.fvp[3 * sd + Q], iq, vq[sd][0], vq[sd][1]);
+  }
+  double bpL, bpR, bqL, bqR;
+  rec(a.bp, iq, bpL, bpR);
+  rec(a.bq, ip, bqL, bqR);
+  const double app = fmax((double)a.app[c.id], (double)a.app[iq[3]]);
+  const double amp = fmax((double)a.amp[c.id], (double)a.amp[iq[3]]);
+  const double aqp = fmax((double)a.apq[c.id], (double)a.apq[ip[3]]);
+  const double aqm = fmax((double)a.amq[c.id], (double)a.amq[ip[3]]);
+  double E[2][2];
+#pragma unroll
+  for (int sa = 0; sa < 2; ++sa)
+#pragma unroll
+    for (int sb = 0; sb < 2; ++sb)
+      E[sa][sb] = vq[sa][sb] * (sb ? bpR : bpL) - vp[sa][sb] * (sa ? bqR : bqL);
+  a.e[c.id] = uct_edge<double>(E[0][0], E[0][1], E[1][0], E[1][1], app, amp, aqp, aqm, bqL, bqR,
+                               bpL, bpR);
+}
+
+template <typename TS>
+void launch_uct(int k, const UctArgs<TS>& a, hipStream_t s) {
+  dim3 grid((a.g.nx + kBlockX - 1) / kBlockX, (a.g.ny + kBlockY - 1) / kBlockY, a.g.nz);
+  dim3 blk(kBlockX, kBlockY);
+  if (k == 0) hipLaunchKernelGGL((k_uct<0, TS>), grid, blk, 0, s, a);
+  else if (k == 1) hipLaunchKernelGGL((k_uct<1, TS>), grid, blk, 0, s, a);
+  else hipLaunchKernelGGL((k_uct<2, TS>), grid, blk, 0, s, a);
+}
+template void launch_uct<double>(int, const UctArgs<double>&, hipStream_t);
+template void launch_uct<float>(int, const UctArgs<float>&, hipStream_t);
+
+// -------------------------------------------------- DER + RK3 stage update
+// L(U) at centres: -sum_d (Fhat(+d face) - Fhat(-d face))/dx_d; at faces:
+// dB_d/dt = -(d_p E_q - d_q E_p), (d, p, q) cyclic.  SSP-RK3 (Shu & Osher):
+// stage 1: U1 = U0 + dt L; stage 2: 3/4 U0 + 1/4 (U1 + dt L);
+// stage 3: 1/3 U0 + 2/3 (U2 + dt L).  Stage 0 writes L only.
+template <int STAGE, typename TS>
+__global__ __launch_bounds__(kThreads) void k_update(UpdArgs<TS> a) {
+  const Cell c = cell_of(a.g);
+  if (!c.valid) return;
+  const int im = minus1(a.g, c, 0), jm = minus1(a.g, c, 1), km = minus1(a.g, c, 2);
+  const int nb[3] = {im, jm, km};
+  const double* ix = a.g.inv_dx;
+  double r[8];
+#pragma unroll
+  for (int n = 0; n < 5; ++n) {
+    double s = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+      s += ((double)a.fhat[d][n][c.id] - (double)a.fhat[d][n][nb[d]]) * ix[d];
+    r[n] = -s;
+  }
+  const double* Ex = a.e[0];
+  const double* Ey = a.e[1];
+  const double* Ez = a.e[2];
+  const double ex0 = Ex[c.id], ey0 = Ey[c.id], ez0 = Ez[c.id];
+  r[5] = -((ez0 - Ez[jm]) * ix[1] - (ey0 - Ey[km]) * ix[2]);
+  r[6] = -((ex0 - Ex[km]) * ix[2] - (ez0 - Ez[im]) * ix[0]);
+  r[7] = -((ey0 - Ey[im]) * ix[0] - (ex0 - Ex[jm]) * ix[1]);
+  if (STAGE == 0) {
+#pragma unroll
+    for (int n = 0; n < 8; ++n) a.rhs_out[n][c.id] = r[n];
+    return;
+  }
+  const double dt = a.sc->dt;
+#pragma unroll
+  for (int n = 0; n < 8; ++n) {
+    const double u = a.u[n][c.id];
+    if (STAGE == 1) {
+      a.u0[n][c.id] = u;
+      a.u[n][c.id] = u + dt * r[n];
+    } else if (STAGE == 2) {
+      a.u[n][c.id] = 0.75 * a.u0[n][c.id] + 0.25 * (u + dt * r[n]);
+    } else {
+      a.u[n][c.id] = (1.0 / 3.0) * a.u0[n][c.id] + (2.0 / 3.0) * (u + dt * r[n]);
+    }
+  }
+}
+
+template <typename TS>
+void launch_update(int stage, const UpdArgs<TS>& a, hipStream_t s) {
+  dim3 grid((a.g.nx + kBlockX - 1) / kBlockX, (a.g.ny + kBlockY - 1) / kBlockY, a.g.nz);
+  dim3 blk(kBlockX, kBlockY);
+  switch (stage) {
+    case 0: hipLaunchKernelGGL((k_update<0, TS>), grid, blk, 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_update<1, TS>), grid, blk, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_update<2, TS>), grid, blk, 0, s, a); break;
+    default: hipLaunchKernelGGL((k_update<3, TS>), grid, blk, 0, s, a); break;
+  }
+}
+template void launch_update<double>(int, const UpdArgs<double>&, hipStream_t);
+template void launch_update<float>(int, const UpdArgs<float>&, hipStream_t);
+
+// ------------------------------------------------------------ timestep
+// dt = cfl / amax (or dt_fixed) once per step, from the first stage's speeds;
+// advances t and the step count and clears the running maximum.
+__global__ void k_dt(DevScalars* sc, double cfl, double dt_fixed) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double amax = __longlong_as_double((long long)sc->amax_bits);
+  const double dt = dt_fixed > 0.0 ? dt_fixed : cfl / amax;
+  if (!(dt > 0.0) || !isfinite(dt)) atomicOr(&sc->err, kErrDt);
+  sc->dt = dt;
+  sc->t = sc->t + dt;
+  sc->step = sc->step + 1;
+  sc->amax_last = amax;
+  sc->amax_bits = 0ull;
+}
+
+void launch_dt(DevScalars* sc, double cfl, double dt_fixed, hipStream_t s) {
+  hipLaunchKernelGGL(k_dt, dim3(1), dim3(64), 0, s, sc, cfl, dt_fixed);
+}
+
+__global__ void k_zero_u64(unsigned long long* p, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0ull;
+}
+
+void launch_zero_u64(unsigned long long* p, size_t n, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+}
+
+__global__ void k_set_time(DevScalars* sc, double t, long long step) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  sc->t = t;
+  sc->step = step;
+}
+
+void launch_set_time(DevScalars* sc, double t, long long step, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_time, dim3(1), dim3(64), 0, s, sc, t, step);
+}
+
+// ------------------------------------------------------------ diagnostics
+// Fixed-order reductions (bitwise reproducible): workgroup b sums a fixed
+// contiguous chunk, threads in a fixed stride, then a fixed LDS tree; a single
+// workgroup combines the partials in order.  Outputs sums of the 8 state
+// arrays and max |div_h B| (div_h B = sum_d (B_d(+) - B_d(-))/dx_d).
+constexpr int kReduceBlocks = 1024;
+constexpr int kReduceThreads = 256;
+
+int reduce_blocks(const GridDims&) { return kReduceBlocks; }
+
+__global__ __launch_bounds__(kReduceThreads) void k_reduce_partial(ReduceArgs a) {
+  __shared__ double sm[9][kReduceThreads];
+  const long long N = (long long)a.g.nx * a.g.ny * a.g.nz;
+  const long long chunk = (N + a.nblocks - 1) / a.nblocks;
+  const long long beg = (long long)blockIdx.x * chunk;
+  const long long end = beg + chunk < N ? beg + chunk : N;
+  double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  const int nxy = a.g.nx * a.g.ny;
+  for (long long q = beg + threadIdx.x; q < end; q += kReduceThreads) {
+    const int id = (int)q;
+    for (int n = 0; n < 8; ++n) acc[n] += a.a[n][id];
+    const int i = id % a.g.nx, j = (id / a.g.nx) % a.g.ny, k = id / nxy;
+    const int im = i == 0 ? id + a.g.nx - 1 : id - 1;
+    const int jm = j == 0 ? id + (a.g.ny - 1) * a.g.nx : id - a.g.nx;
+    const int km = k == 0 ? id + (a.g.nz - 1) * nxy : id - nxy;
+    double dv = 0.0;
+    dv += (a.bf[0][id] - a.bf[0][im]) * a.g.inv_dx[0];
+    dv += (a.bf[1][id] - a.bf[1][jm]) * a.g.inv_dx[1];
+    dv += (a.bf[2][id] - a.bf[2][km]) * a.g.inv_dx[2];
+    acc[8] = fmax(acc[8], fabs(dv));
+  }
+  for (int n = 0; n < 9; ++n) sm[n][threadIdx.x] = acc[n];
+  __syncthreads();
+  for (int w = kReduceThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      for (int n = 0; n < 8; ++n) sm[n][threadIdx.x] += sm[n][threadIdx.x + w];
+      sm[8][threadIdx.x] = fmax(sm[8][threadIdx.x], sm[8][threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 9) a.partial[blockIdx.x * 9 + threadIdx.x] = sm[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(kReduceThreads) void k_reduce_final(ReduceArgs a) {
+  __shared__ double sm[9][kReduceThreads];
+  double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int b = threadIdx.x; b < a.nblocks; b += kReduceThreads) {
+    for (int n = 0; n < 8; ++n) acc[n] += a.partial[b * 9 + n];
+    acc[8] = fmax(acc[8], a.partial[b * 9 + 8]);
+  }
+  for (int n = 0; n < 9; ++n) sm[n][threadIdx.x] = acc[n];
+  __syncthreads();
+  for (int w = kReduceThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      for (int n = 0; n < 8; ++n) sm[n][threadIdx.x] += sm[n][threadIdx.x + w];
+      sm[8][threadIdx.x] = fmax(sm[8][threadIdx.x], sm[8][threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 9) a.sc->reduce_out[threadIdx.x] = sm[threadIdx.x][0];
+}
+
+void launch_reduce(const ReduceArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_partial, dim3(a.nblocks), dim3(kReduceThreads), 0, s, a);
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kReduceThreads), 0, s, a);
+}
+
+}  // namespace srmhd

@@ -1,0 +1,133 @@
+// srmhd_kernels.hpp -- kernel argument blocks and launchers shared by the
+// kernel and C-ABI translation units of libsrmhd.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace srmhd {
+
+constexpr int kBlockX = 64;  // one wavefront along x
+constexpr int kBlockY = 4;   // four wavefronts per workgroup
+constexpr int kThreads = kBlockX * kBlockY;
+
+// Replicated device counters (spread over kReplicas copies so that the
+// per-workgroup atomics of 10^5 workgroups do not queue on one address).
+constexpr int kReplicas = 64;
+enum Counter {
+  CNT_ITERS = 0,
+  CNT_CALLS = 1,
+  CNT_HIST0 = 2,  // 32 bins
+  CNT_FAIL = 34,
+  CNT_FALLBACK = 35,
+  CNT_FLOOR = 36,
+  CNT_MLPFB = 37,
+  CNT_N = 40
+};
+
+// Device-resident scalars at the head of the work buffer.
+struct DevScalars {
+  unsigned long long amax_bits;  // running max of the CFL sum (bits of a +double)
+  double amax_last;
+  double dt;
+  double t;
+  long long step;
+  unsigned int err;
+  unsigned int pad;
+  double reduce_out[16];  // diagnostics results
+};
+
+struct GridDims {
+  int nx, ny, nz;
+  double inv_dx[3];
+};
+
+struct C2PArgs {
+  GridDims g;
+  const double* cons[5];
+  const double* bf[3];
+  double* W;
+  double* prim64[8];  // FP64 outputs (or null)
+  float* prim32[8];   // FP32 copies for the mixed form (or null)
+  double gam, tol, pfloor;
+  int maxit;
+  int guess;  // 0 = previous W, 2 = cold start
+  unsigned long long* counters;
+  unsigned int* err;
+};
+
+template <typename TS>
+struct FluxArgs {
+  GridDims g;
+  const TS* prim[8];   // rho, vx, vy, vz, p, Bcx, Bcy, Bcz
+  const double* bn;    // face-normal B of this direction
+  TS* fhat[5];         // D, Sx, Sy, Sz, U fluxes at the +face
+  TS* ap;
+  TS* am;
+  TS* fv[6];           // left vx, vy, vz; right vx, vy, vz at the +face
+  const TS* apm_other[4];  // a+/a- of the other two directions (CFL fusion)
+  unsigned long long* amax_bits;
+  double gam;
+  int riemann;
+  unsigned long long* counters;
+};
+
+template <typename TS>
+struct UctArgs {
+  GridDims g;
+  const TS* fvp[6];   // p-face velocity states (left xyz, right xyz)
+  const TS* app;      // a+ at p faces
+  const TS* amp;      // a- at p faces
+  const TS* apq;      // a+ at q faces
+  const TS* amq;      // a- at q faces
+  const double* bp;   // face B_p
+  const double* bq;   // face B_q
+  double* e;          // edge field E_k
+};
+
+template <typename TS>
+struct UpdArgs {
+  GridDims g;
+  const TS* fhat[3][5];
+  const double* e[3];
+  double* u[8];       // state: D, Sx, Sy, Sz, U, Bx, By, Bz (in place)
+  double* u0[8];      // RK register U^n
+  double* rhs_out[8]; // stage 0: write L(U) here instead of updating
+  const DevScalars* sc;
+};
+
+struct InitArgs {
+  GridDims g;
+  const double* prim5[5];
+  const double* bf_in[3];
+  double* cons[5];
+  double* bf[3];
+  double* W;
+  double gam;
+};
+
+struct ReduceArgs {
+  GridDims g;
+  const double* a[8];
+  const double* bf[3];
+  double* partial;  // [nblocks][9]
+  int nblocks;
+  DevScalars* sc;
+};
+
+// Launchers (srmhd_kernels.hip).  All asynchronous on `stream`.
+void launch_init(const InitArgs& a, hipStream_t s);
+void launch_c2p(const C2PArgs& a, bool stats, hipStream_t s);
+template <typename TS>
+void launch_flux(int dir, const FluxArgs<TS>& a, bool cfl, bool stats, hipStream_t s);
+template <typename TS>
+void launch_uct(int k, const UctArgs<TS>& a, hipStream_t s);
+template <typename TS>
+void launch_update(int stage, const UpdArgs<TS>& a, hipStream_t s);
+void launch_dt(DevScalars* sc, double cfl, double dt_fixed, hipStream_t s);
+void launch_zero_u64(unsigned long long* p, size_t n, hipStream_t s);
+void launch_set_time(DevScalars* sc, double t, long long step, hipStream_t s);
+void launch_reduce(const ReduceArgs& a, hipStream_t s);
+int reduce_blocks(const GridDims& g);
+
+}  // namespace srmhd

@@ -1,0 +1,349 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle on
+the same seeded inputs.  Plain FP64 bar: per-variable L1 relative error
+<= 1e-12 (sum |gpu - oracle| / max(sum |oracle|, N s_q), s_q = v_A for
+velocities, B0 for fields, 1 otherwise); element-wise checks of the spatial
+operator on rough random states and on sampled cells at 256^3."""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle as O  # noqa: E402
+from paper_2401_03008_amd import inputs as I  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+VA = I.cpa_alfven_speed()
+SCALE = [1.0, VA, VA, VA, 1.0, 1.0, 1.0, 1.0]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2401_03008_amd.solver import Solver  # noqa: F401
+    O.build(force=False)
+
+
+def _solver(shape, **kw):
+    from paper_2401_03008_amd.solver import Solver
+    nz, ny, nx = shape
+    print(f"[gpu] Solver {nx}x{ny}x{nz} {kw}", flush=True)
+    return Solver(nx, ny, nz, **kw)
+
+
+def l1rel(a, b, s):
+    return np.abs(a - b).sum() / max(np.abs(b).sum(), a.size * s)
+
+
+def _oracle(shape, **kw):
+    nz, ny, nx = shape
+    return O.Grid(nx, ny, nz, **kw)
+
+
+def _gpu_prims(S):
+    P = S.primitives()
+    torch.cuda.synchronize()
+    return P.cpu().numpy()
+
+
+def _rough_state(shape, seed):
+    """rho in [0.5, 2], p in [0.1, 1], |v| up to 0.99 in random directions,
+    face B ~ N(0, 1): exercises every MP5 branch and the first-order
+    fallback."""
+    rng = np.random.default_rng(seed)
+    rho = rng.uniform(0.5, 2.0, shape)
+    p = rng.uniform(0.1, 1.0, shape)
+    d = rng.normal(size=(3,) + shape)
+    d /= np.linalg.norm(d, axis=0)
+    v = d * rng.uniform(0.0, 0.99, shape)
+    bf = [np.ascontiguousarray(rng.normal(size=shape)) for _ in range(3)]
+    prim5 = [np.ascontiguousarray(a) for a in (rho, v[0], v[1], v[2], p)]
+    return prim5, bf
+
+
+# ----------------------------------------------------------------- inversion
+@pytest.mark.parametrize("shape", [(16, 24, 72), (8, 8, 8)])
+def test_init_and_inversion_match_oracle(shape):
+    prim5, bf = _rough_state(shape, 1)
+    S = _solver(shape)
+    S.init(prim5, bf)
+    P = _gpu_prims(S)
+    g = _oracle(shape)
+    cons, W = g.init(prim5, bf)
+    np.testing.assert_allclose(S.cons.cpu().numpy(), np.stack(cons), rtol=1e-14, atol=1e-14)
+    np.testing.assert_array_equal(S.bface.cpu().numpy(), np.stack(bf))
+    Pr, it, nf = g.c2p(cons, bf, W)
+    assert nf == 0
+    for q in range(8):
+        np.testing.assert_allclose(P[q], Pr[q], rtol=1e-12, atol=1e-13)
+    for q in range(5):
+        np.testing.assert_allclose(P[q], prim5[q], rtol=1e-12, atol=1e-13)
+    np.testing.assert_allclose(S.W.cpu().numpy(), W, rtol=1e-13)
+    d = S.diagnostics()
+    assert d["newton_calls"] == math.prod(shape)
+    assert d["c2p_failures"] == 0 and d["error_word"] == 0
+    S.close()
+
+
+def test_inversion_cold_start_histogram():
+    """Cold start (W0 = U): same converged primitives; the Newton histogram
+    agrees with the oracle's to within a few cells (rounding may move an
+    inversion by one iteration)."""
+    shape = (8, 16, 64)
+    prim5, bf = _rough_state(shape, 2)
+    S = _solver(shape, guess="cold")
+    S.init(prim5, bf)
+    S.reset_counters()
+    P = _gpu_prims(S)
+    d = S.diagnostics()
+    g = _oracle(shape)
+    cons, W = g.init(prim5, bf)
+    W[:] = -1.0
+    Pr, it, nf = g.c2p(cons, bf, W)
+    for q in range(8):
+        np.testing.assert_allclose(P[q], Pr[q], rtol=1e-11, atol=1e-12)
+    hist = np.bincount(np.minimum(it.ravel(), 31), minlength=32)
+    assert np.abs(np.array(d["newton_hist"]) - hist).sum() <= 0.01 * it.size
+    assert d["newton_iters"] == pytest.approx(it.sum(), rel=0.01)
+    S.close()
+
+
+# ----------------------------------------------------------- spatial operator
+@pytest.mark.parametrize("shape,seed", [((12, 20, 72), 3), ((8, 8, 8), 4), ((9, 10, 11), 5)])
+def test_rhs_matches_oracle_elementwise(shape, seed):
+    """L(U) element by element on rough random states (ragged tiles, every
+    MP5 branch, first-order fallbacks); amax exactly."""
+    prim5, bf = _rough_state(shape, seed)
+    S = _solver(shape)
+    S.init(prim5, bf)
+    R, amax = S.rhs()
+    torch.cuda.synchronize()
+    R = R.cpu().numpy()
+    d = S.diagnostics()
+    g = _oracle(shape)
+    cons, W = g.init(prim5, bf)
+    Pr, _, _ = g.c2p(cons, bf, W)
+    Rr, amax_r = g.rhs(Pr, bf)
+    assert d["recon_fallbacks"] == g.stats.recon_fallbacks > 0
+    assert amax.item() == pytest.approx(amax_r, rel=1e-13)
+    for q in range(8):
+        scale = np.abs(Rr[q]).max()
+        np.testing.assert_allclose(R[q], Rr[q], rtol=0, atol=1e-11 * scale, err_msg=f"comp {q}")
+
+
+@pytest.mark.parametrize("riemann", ["hll", "llf"])
+def test_rhs_cpa_diagonal(riemann):
+    shape = (16, 16, 16)
+    prim5, bf, _ = I.cpa(16, diagonal=True)
+    S = _solver(shape, riemann=riemann)
+    S.init(prim5, bf)
+    R, amax = S.rhs()
+    R = R.cpu().numpy()
+    g = _oracle(shape, riemann=1 if riemann == "llf" else 0)
+    cons, W = g.init(prim5, bf)
+    Pr, _, _ = g.c2p(cons, bf, W)
+    Rr, amax_r = g.rhs(Pr, bf)
+    assert amax.item() == pytest.approx(amax_r, rel=1e-14)
+    # L(U) is a difference of O(1) fluxes over dx; for components that nearly
+    # cancel (D of the CPA) the round-off floor is ~eps/dx, not eps*|L(U)|
+    for q in range(8):
+        tol = 1e-12 * max(np.abs(Rr[q]).max(), 16.0)
+        np.testing.assert_allclose(R[q], Rr[q], rtol=0, atol=tol)
+
+
+# ------------------------------------------------------------- full steps
+def _step_both(shape, prim5, bf, nsteps, **kw):
+    okw = {k: v for k, v in kw.items() if k in ("dt_fixed", "cfl", "pfloor")}
+    if kw.get("riemann") == "llf":
+        okw["riemann"] = 1
+    S = _solver(shape, **kw)
+    S.init(prim5, bf)
+    S.step(nsteps)
+    P = _gpu_prims(S)
+    t, st, dt = S.time()
+    d = S.diagnostics()
+    Bg = S.bface.cpu().numpy()
+    S.close()
+    g = _oracle(shape, **okw)
+    cons, W = g.init(prim5, bf)
+    bfo = [b.copy() for b in bf]
+    tr, dtr, nf = g.step(cons, bfo, W, nsteps)
+    Pr, _, _ = g.c2p(cons, bfo, W)
+    return P, Bg, (t, st, dt, d), Pr, np.stack(bfo), (tr, dtr, nf)
+
+
+def test_step_parity_cpa_axis_32():
+    """Config 1: x-aligned CPA, 32^3, rho = p = B0 = eta = 1, CFL 0.5, 20
+    steps: L1 relative <= 1e-12 per primitive; dt to 1e-14."""
+    prim5, bf, _ = I.cpa(32, diagonal=False)
+    P, Bg, (t, st, dt, d), Pr, Br, (tr, dtr, nf) = _step_both((32, 32, 32), prim5, bf, 20)
+    assert st == 20 and nf == 0 and d["c2p_failures"] == 0 and d["recon_fallbacks"] == 0
+    assert dt == pytest.approx(dtr, rel=1e-14)
+    assert t == pytest.approx(tr, rel=1e-14)
+    for q in range(8):
+        assert l1rel(P[q], Pr[q], SCALE[q]) <= 1e-12, q
+    for k in range(3):
+        assert l1rel(Bg[k], Br[k], 1.0) <= 1e-12
+    # B_x stays exactly B0 and the state stays y/z independent
+    assert np.all(Bg[0] == 1.0)
+    assert np.all(P == P[:, :1, :1, :])
+
+
+@pytest.mark.parametrize("riemann", ["hll", "llf"])
+def test_step_parity_cpa_diagonal(riemann):
+    prim5, bf, _ = I.cpa(24, diagonal=True)
+    P, Bg, (t, st, dt, d), Pr, Br, (tr, dtr, nf) = _step_both(
+        (24, 24, 24), prim5, bf, 8, riemann=riemann)
+    assert dt == pytest.approx(dtr, rel=1e-13)
+    for q in range(8):
+        assert l1rel(P[q], Pr[q], SCALE[q]) <= 1e-12, q
+    for k in range(3):
+        assert l1rel(Bg[k], Br[k], 1.0) <= 1e-12
+
+
+def test_step_parity_turbulence_ragged():
+    """Ragged box (40 x 24 x 16) of the turbulence set-up (Gamma <= 2)."""
+    shape = (16, 24, 40)
+    prim5, bf = I.turbulence((40, 24, 16), gamma_max=2.0)
+    P, Bg, (t, st, dt, d), Pr, Br, (tr, dtr, nf) = _step_both(shape, prim5, bf, 4, pfloor=1e-10)
+    assert nf == 0 and d["c2p_failures"] == 0
+    assert dt == pytest.approx(dtr, rel=1e-12)
+    for q in range(8):
+        assert l1rel(P[q], Pr[q], 1.0) <= 1e-12, q
+
+
+# ------------------------------------------------- full size, bench launch shape
+def test_rhs_sampled_cells_256():
+    """Diagonal CPA at 256^3 (the benchmark's size and launch shape): L(U) on
+    2048 sampled cells (including the box corners) against the oracle's
+    per-cell evaluation."""
+    n = 256
+    prim5, bf, _ = I.cpa(n, diagonal=True)
+    S = _solver((n, n, n))
+    S.init(prim5, bf)
+    R, amax = S.rhs()
+    R = R.reshape(8, -1)
+    rng = np.random.default_rng(256)
+    cells = np.unique(np.concatenate([rng.choice(n ** 3, 2040, replace=False),
+                                      [0, n - 1, n * n - 1, n ** 3 - 1, n ** 3 - n, (n - 1) * n * n]]))
+    Rg = R[:, torch.as_tensor(cells, device=R.device)].cpu().numpy().T
+    S.close()
+    g = O.Grid(n)
+    cons, W = g.init(prim5, bf)
+    Pr, _, nf = g.c2p(cons, bf, W)
+    assert nf == 0
+    Rr = g.rhs_cells(Pr, bf, cells)
+    for q in range(8):
+        tol = 1e-12 * max(np.abs(Rr[:, q]).max(), float(n))
+        np.testing.assert_allclose(Rg[:, q], Rr[:, q], rtol=0, atol=tol)
+
+
+def test_invariants_256_bench_config():
+    """The benchmark workload itself (diagonal CPA 256^3, FP64, CFL 0.5):
+    sums of D, S, U, face B conserved to round-off and max |div_h B| stays at
+    its initial round-off level over 20 steps; no inversion failures."""
+    n = 256
+    prim5, bf, _ = I.cpa(n, diagonal=True)
+    S = _solver((n, n, n))
+    S.init(prim5, bf)
+    d0 = S.diagnostics()
+    S.step(20)
+    d1 = S.diagnostics()
+    N = n ** 3
+    scale = [1.1 * N, 1.0 * N, 1.0 * N, 1.0 * N, 6.0 * N, 1.5 * N, 1.5 * N, 1.5 * N]
+    for q in range(8):
+        assert abs(d1["sums"][q] - d0["sums"][q]) <= 1e-13 * scale[q], q
+    assert d0["divb_max"] / n < 1e-12 and d1["divb_max"] / n < 1e-12
+    assert d1["c2p_failures"] == 0 and d1["recon_fallbacks"] == 0 and d1["step"] == 20
+    S.close()
+
+
+def test_convergence_gpu_64_128_256():
+    """Second order (HO=NO) on the diagonal wave vs the exact solution,
+    dt = 0.2 dx, t_f = 0.078125 (25/50/100 steps)."""
+    errs = []
+    for n in (64, 128, 256):
+        prim5, bf, _ = I.cpa(n, diagonal=True)
+        S = _solver((n, n, n), dt_fixed=0.2 / n)
+        S.init(prim5, bf)
+        S.step(int(round(0.078125 * n / 0.2)))
+        t, _, _ = S.time()
+        P = _gpu_prims(S)
+        Bg = S.bface.cpu().numpy()
+        S.close()
+        ex5, exbf, _ = I.cpa(n, diagonal=True, t=t)
+        errs.append(np.mean([np.abs(P[q] - ex5[q]).mean() for q in (1, 2, 3)]
+                            + [np.abs(Bg[d] - exbf[d]).mean() for d in range(3)]))
+    o1, o2 = math.log2(errs[0] / errs[1]), math.log2(errs[1] / errs[2])
+    print("[gpu] errors", errs, "orders", o1, o2, flush=True)
+    assert o1 > 1.8 and o2 > 1.8
+
+
+# ---------------------------------------------------- host-forced failures
+def test_nonfinite_input_reported():
+    shape = (8, 8, 8)
+    prim5, bf, _ = I.cpa(8, diagonal=True)
+    S = _solver(shape)
+    S.init(prim5, bf)
+    S.cons[0, 3, 4, 5] = float("nan")
+    S.step(1)
+    d = S.diagnostics(raise_on_error=False)
+    assert d["rc"] == -4 and d["error_word"] & 2
+    S.close()
+
+
+def test_maxit_one_counts_failures():
+    shape = (8, 8, 8)
+    prim5, bf, _ = I.cpa(8, diagonal=True)
+    S = _solver(shape, newton_maxit=1)
+    S.init(prim5, bf)
+    S.W.mul_(1.5)  # poor guess: one iteration cannot converge
+    S.primitives()
+    d = S.diagnostics(raise_on_error=False)
+    assert d["rc"] == -3 and d["c2p_failures"] > 0 and d["error_word"] & 1
+    S.close()
+
+
+def test_step_before_init_is_state_error():
+    from paper_2401_03008_amd import binding as B
+    S = _solver((8, 8, 8))
+    with pytest.raises(B.SrmhdError) as e:
+        S.step(1)
+    assert e.value.code == B.SRMHD_E_STATE
+    S.close()
+
+
+# -------------------------------------------------- determinism / checkpoint
+def test_bitwise_determinism_and_checkpoint_restart():
+    shape = (32, 32, 32)
+    prim5, bf, _ = I.cpa(32, diagonal=True)
+    S = _solver(shape)
+    S.init(prim5, bf)
+    S.step(6)
+    a = S.cons.clone(), S.bface.clone()
+    S.init(prim5, bf)
+    S.step(3)
+    ck = S.checkpoint()
+    S.step(5)  # run past, then go back
+    S.restore(ck)
+    S.step(3)
+    assert torch.equal(S.cons, a[0]) and torch.equal(S.bface, a[1])
+    t, st, _ = S.time()
+    assert st == 6
+    S.close()
+
+
+def test_kernel_timing_counts_launches():
+    shape = (32, 32, 32)
+    prim5, bf, _ = I.cpa(32, diagonal=True)
+    S = _solver(shape)
+    S.init(prim5, bf)
+    S.kernel_timing(True)
+    S.step(2)
+    kt = S.kernel_times()
+    assert kt["c2p"][1] == 6 and kt["flux_x"][1] == 6 and kt["update"][1] == 6 and kt["dt"][1] == 2
+    assert all(v[0] > 0 for k, v in kt.items())
+    S.close()
