@@ -47,6 +47,51 @@ KERNEL_UNITS = {
 }
 
 
+def profiled_traffic(kernel_name):
+    """HBM bytes per launch of `kernel_name` from the committed rocprofv3
+    summaries (FETCH_SIZE and WRITE_SIZE scaled by a plain copy's readings),
+    or None when the kernel source changed since the counters were taken."""
+    import glob
+    import hashlib
+    src = os.path.join(ROOT, "paper_2401_03008_amd", "csrc", "srmhd_kernels.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.txt"))):
+        txt = open(f).read()
+        if f"srmhd_kernels.hip: {sha}" not in txt:
+            continue
+        for line in txt.splitlines():
+            if line.startswith("traffic_bytes_per_launch ") and kernel_name in line:
+                return int(line.rsplit(":", 1)[1])
+    return None
+
+
+def run_form(n, precision, steps, warmup):
+    """Mcell-updates/s of one form on the diagonal CPA at n^3."""
+    import torch
+    from paper_2401_03008_amd import inputs
+    from paper_2401_03008_amd.solver import Solver
+    prim5, bf, _ = inputs.cpa(n, diagonal=True, device="cuda")
+    S = Solver(n, precision=precision, collect_stats=False)
+    S.init(prim5, bf)
+    del prim5, bf
+    S.step(warmup)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(S.stream)
+    S.step(steps)
+    e1.record(S.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    S.close()
+    del S
+    torch.cuda.empty_cache()
+    v = n ** 3 * steps / (ms / 1e3) / 1e6
+    return {"cells": n ** 3, "steps": steps, "ms_per_step": round(ms / steps, 3),
+            "Mcell_updates_per_s": round(v, 1),
+            "hbm_roofline_frac_step": round(v * 1e6 * STEP_BYTES / (HBM_PEAK_GBS * 1e9), 4)}
+
+
 def cpu_baseline(seconds_target=15.0):
     """The oracle (as it stands) on the same wave at 64^3, all host cores."""
     import oracle
@@ -79,6 +124,9 @@ def main():
     ap.add_argument("--stats", action="store_true", help="collect Newton statistics while timed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the per-form runs (plain FP64 and mixed) at --forms-n")
+    ap.add_argument("--forms-n", type=int, default=512)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of MIB MiB (a reference "
                          "kernel for hardware byte counters)")
@@ -106,7 +154,7 @@ def main():
 
     n = args.n
     print(f"[bench] building the {n}^3 diagonal CPA", file=sys.stderr, flush=True)
-    prim5, bf, _ = inputs.cpa(n, diagonal=True)
+    prim5, bf, _ = inputs.cpa(n, diagonal=True, device="cuda")
     S = Solver(n, precision=args.precision, collect_stats=args.stats)
     S.init(prim5, bf)
     del prim5, bf
@@ -156,11 +204,22 @@ def main():
         else:
             roof = {"bound": "alu", "achieved": round(tfl, 3), "peak": fpeak,
                     "unit": "TFLOP/s", "frac": round(tfl / fpeak, 4), "traffic": None}
+        if args.precision == "fp64" and n == 256:
+            dom_name = {"update": "k_update<2, double>"}.get(dom)
+            tr = profiled_traffic(dom_name) if dom_name else None
+            roof["traffic"] = tr
         roof.update({"kernel": dom, "avg_ms": round(kernels[dom]["avg_ms"], 4),
                      "alg_bytes_per_launch": bytes_per, "alg_flops_per_launch": flops_per,
                      "alu_tflops": round(tfl, 3), "hbm_gbs": round(gbs, 1)})
         print(f"[bench] kernel timing: {json.dumps(kernels)}", file=sys.stderr, flush=True)
     S.close()
+
+    forms = None
+    if not args.no_forms:
+        forms = {}
+        for prec in ("fp64", "mixed"):
+            print(f"[bench] form {prec} at {args.forms_n}^3", file=sys.stderr, flush=True)
+            forms[prec] = run_form(args.forms_n, prec, max(5, args.steps // 2), 2)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -188,6 +247,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "kernels": kernels,
+        "forms": forms,
         "final_step_dt": diag["dt"],
     }
     print(json.dumps(line))

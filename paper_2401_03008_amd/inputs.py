@@ -55,43 +55,55 @@ def cpa_period(diagonal: bool, rho=1.0, p=1.0, B0=1.0, eta=1.0, gam=GAMMA_AD,
     return 2 * math.pi / (k * cpa_alfven_speed(rho, p, B0, eta, gam))
 
 
-def _fields_at(x, y, z, t, diagonal, rho, p, B0, eta, gam, L):
+def _fields_at(x, y, z, t, diagonal, rho, p, B0, eta, gam, L, xp=np):
     XYZ = cpa_basis(diagonal)
     kv = cpa_wavevector(diagonal, L)
     va = cpa_alfven_speed(rho, p, B0, eta, gam)
-    phi = kv[0] * x + kv[1] * y + kv[2] * z - np.linalg.norm(kv) * va * t
-    c, s = np.cos(phi), np.sin(phi)
+    phi = kv[0] * x + kv[1] * y + kv[2] * z - float(np.linalg.norm(kv)) * va * t
+    c, s = xp.cos(phi), xp.sin(phi)
     B = [B0 * XYZ[0][d] + eta * B0 * (c * XYZ[1][d] + s * XYZ[2][d]) for d in range(3)]
     v = [-va * eta * (c * XYZ[1][d] + s * XYZ[2][d]) for d in range(3)]
     return v, B
 
 
 def cpa(n, diagonal=True, t=0.0, rho=1.0, p=1.0, B0=1.0, eta=1.0, gam=GAMMA_AD,
-        L=(1.0, 1.0, 1.0)):
+        L=(1.0, 1.0, 1.0), device=None):
     """Exact CPA wave at time t on an (nz, ny, nx) grid.
 
     n is an int (cube) or (nx, ny, nz).  Returns (prim5, bf, Bc): prim5 =
     [rho, vx, vy, vz, p] at cell centres, bf = face B point-sampled at face
-    centres, Bc = the exact B at cell centres (for error measurement)."""
+    centres, Bc = the exact B at cell centres (for error measurement).
+    numpy float64 arrays, or torch float64 tensors on `device` if given."""
     nx, ny, nz = (n, n, n) if np.isscalar(n) else n
     dx, dy, dz = L[0] / nx, L[1] / ny, L[2] / nz
-    xc = (np.arange(nx) + 0.5) * dx
-    yc = (np.arange(ny) + 0.5) * dy
-    zc = (np.arange(nz) + 0.5) * dz
-    xf, yf, zf = (np.arange(nx) + 1.0) * dx, (np.arange(ny) + 1.0) * dy, (np.arange(nz) + 1.0) * dz
-    Z, Y, X = np.meshgrid(zc, yc, xc, indexing="ij")
-    v, Bc = _fields_at(X, Y, Z, t, diagonal, rho, p, B0, eta, gam, L)
-    shape = (nz, ny, nx)
-    prim5 = [np.full(shape, rho), v[0], v[1], v[2], np.full(shape, p)]
+    if device is None:
+        xp, ar = np, (lambda m, o, h: (np.arange(m) + o) * h)
+        mesh = lambda a, b, c: np.meshgrid(a, b, c, indexing="ij")
+        full = lambda v: np.full((nz, ny, nx), float(v))
+        cont = np.ascontiguousarray
+    else:
+        import torch
+        xp = torch
+        ar = lambda m, o, h: (torch.arange(m, dtype=torch.float64, device=device) + o) * h
+        mesh = lambda a, b, c: torch.meshgrid(a, b, c, indexing="ij")
+        full = lambda v: torch.full((nz, ny, nx), float(v), dtype=torch.float64, device=device)
+        cont = lambda a: a.contiguous()
+    xc, yc, zc = ar(nx, 0.5, dx), ar(ny, 0.5, dy), ar(nz, 0.5, dz)
+    xf, yf, zf = ar(nx, 1.0, dx), ar(ny, 1.0, dy), ar(nz, 1.0, dz)
+    Z, Y, X = mesh(zc, yc, xc)
+    v, Bc = _fields_at(X, Y, Z, t, diagonal, rho, p, B0, eta, gam, L, xp)
+    del X, Y, Z
+    prim5 = [full(rho), cont(v[0]), cont(v[1]), cont(v[2]), full(p)]
+    del v
     bf = []
     for d in range(3):
         coords = [xc, yc, zc]
         coords[d] = [xf, yf, zf][d]
-        Zf, Yf, Xf = np.meshgrid(coords[2], coords[1], coords[0], indexing="ij")
-        _, Bd = _fields_at(Xf, Yf, Zf, t, diagonal, rho, p, B0, eta, gam, L)
-        bf.append(np.ascontiguousarray(Bd[d]))
-    prim5 = [np.ascontiguousarray(a, dtype=np.float64) for a in prim5]
-    return prim5, bf, [np.ascontiguousarray(b) for b in Bc]
+        Zf, Yf, Xf = mesh(coords[2], coords[1], coords[0])
+        _, Bd = _fields_at(Xf, Yf, Zf, t, diagonal, rho, p, B0, eta, gam, L, xp)
+        bf.append(cont(Bd[d]))
+        del Zf, Yf, Xf, Bd
+    return prim5, bf, [cont(b) for b in Bc]
 
 
 def turbulence(n, sigma0=10.0, beta0=0.1, B0=1.0, nmodes=16, kmax=2, gamma_max=5.0,
