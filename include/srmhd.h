@@ -62,7 +62,8 @@ typedef struct {
   double dt_fixed;  /* > 0: fixed dt instead of the CFL rule */
   int riemann;      /* SRMHD_HLL or SRMHD_LLF */
   int precision;    /* SRMHD_FP64, or SRMHD_MIXED: REC + face fluxes in FP32 */
-  int guess;        /* SRMHD_GUESS_PREV, _MLP (needs srmhd_set_mlp) or _COLD */
+  int guess;        /* SRMHD_GUESS_PREV, _COLD, or _MLP (needs srmhd_set_mlp
+                       before the first step) */
   int newton_maxit; /* Newton iteration cap, 1..1000 (50) */
   double newton_tol;/* relative step tolerance on W (1e-14) */
   double pfloor;    /* pressure floor as a fraction of rho; 0 = none */
@@ -162,6 +163,75 @@ int srmhd_set_time(srmhd_ctx *ctx, double t, long step);
 #define SRMHD_NKCLASS 9
 int srmhd_kernel_timing(srmhd_ctx *ctx, int enable);
 int srmhd_get_kernel_times(srmhd_ctx *ctx, double *ms, long *launches);
+
+/* ---------------------------------------------------------------------
+ * Learned Newton guess (not part of the paper; the inversion it seeds is the
+ * Sec. 3 Newton step): a 5 -> 64 -> 64 -> 2 ReLU network, BF16 weights, FP32
+ * accumulation on the matrix cores.  Inputs: the five invariants of a
+ * conserved state on which the inversion depends, log(U/D), |S|/U, B^2/U,
+ * tau^2/(S^2 B^2 + 1e-300), log D (tau = S.B), standardised.  Outputs: the
+ * standardised log(p/D) and log Gamma of the converged inversion, giving
+ * W0 = D Gamma + g/(g-1) p Gamma^2.  Newton from the previous W stays the
+ * fallback (when Newton from W0 does not converge or W0 is unusable) and the
+ * convergence test is unchanged, so results agree with the plain form to the
+ * Newton tolerance.
+ *
+ * Parameter vector, FP32 master and BF16 copy in the same layout (rows are
+ * output units): W1[64][5] | b1[64] | W2[64][64] | b2[64] | W3[2][64] | b3[2].
+ * Training arrays are row-major: x (batch x 5), y and t (batch x 2).
+ * ------------------------------------------------------------------- */
+#define SRMHD_MLP_NPARAM 4674
+#define SRMHD_MLP_OFF_W1 0
+#define SRMHD_MLP_OFF_B1 320
+#define SRMHD_MLP_OFF_W2 384
+#define SRMHD_MLP_OFF_B2 4480
+#define SRMHD_MLP_OFF_W3 4544
+#define SRMHD_MLP_OFF_B3 4672
+
+/* Use the network (device params: FP32 biases and BF16 weights, caller-owned,
+ * kept by pointer) for the guess.  norm (host, 14 floats): feature means[5],
+ * feature std[5], output means[2], output std[2].  Asynchronous. */
+int srmhd_set_mlp(srmhd_ctx *ctx, const float *params, const uint16_t *w_bf16,
+                  const float *norm);
+
+/* Switch the Newton guess (SRMHD_GUESS_*; _MLP needs srmhd_set_mlp). */
+int srmhd_set_guess(srmhd_ctx *ctx, int guess);
+
+/* Training pairs from the current state: each cell is kept with probability
+ * frac (counter-based hash of its index and seed), inverted from the stored W
+ * (W not modified); feats (device, cap x 5) get its features, targets
+ * (device, cap x 2) log(p/D) and log Gamma.  *n_out (host) = pairs written
+ * (<= cap).  Syncs. */
+int srmhd_harvest(srmhd_ctx *ctx, float *feats, float *targets, int cap,
+                  double frac, unsigned seed, int *n_out);
+
+/* Scratch (device, 256-B aligned) for one batch of forward + backward; 0 if
+ * batch is out of range (1..524288). */
+size_t srmhd_mlp_cache_bytes(int batch);
+
+/* w_bf16 = round-to-nearest-even BF16 of params (n values). Asynchronous. */
+int srmhd_mlp_quantize(const float *params, uint16_t *w_bf16, int n, void *stream);
+
+/* y (batch x 2, device) = network(x); keeps activations in cache for the
+ * backward pass.  All pointers device.  Asynchronous on stream. */
+int srmhd_mlp_forward(const float *params, const uint16_t *w_bf16, const float *x,
+                      float *y, void *cache, int batch, void *stream);
+
+/* Mean squared error over the 2*batch outputs into *loss (device) and its
+ * gradient with respect to y into cache.  Asynchronous. */
+int srmhd_mlp_loss_grad(const float *y, const float *t, void *cache, float *loss,
+                        int batch, void *stream);
+
+/* grad (device, SRMHD_MLP_NPARAM floats) = d loss / d params, from the cache
+ * of the last forward + loss_grad with the same batch.  Asynchronous. */
+int srmhd_mlp_backward(const uint16_t *w_bf16, void *cache, float *grad, int batch,
+                       void *stream);
+
+/* One Adam step (Kingma & Ba 2015; t counts from 1) on the FP32 master
+ * params with moments m, v; rewrites the BF16 copy.  Asynchronous. */
+int srmhd_mlp_adam(float *params, uint16_t *w_bf16, float *m, float *v,
+                   const float *grad, int n, float lr, float beta1, float beta2,
+                   float eps, int t, void *stream);
 
 /* Message of the last failure on ctx (NULL ctx: last creation failure). */
 const char *srmhd_last_error(const srmhd_ctx *ctx);

@@ -89,6 +89,18 @@ def lib():
         L.srmhd_get_time.argtypes = [_CTX, C.POINTER(C.c_double), C.POINTER(C.c_long),
                                      C.POINTER(C.c_double)]
         L.srmhd_set_time.argtypes = [_CTX, C.c_double, C.c_long]
+        L.srmhd_set_mlp.argtypes = [_CTX, _VP, _VP, C.POINTER(C.c_float)]
+        L.srmhd_set_guess.argtypes = [_CTX, C.c_int]
+        L.srmhd_harvest.argtypes = [_CTX, _VP, _VP, C.c_int, C.c_double, C.c_uint,
+                                    C.POINTER(C.c_int)]
+        L.srmhd_mlp_cache_bytes.argtypes = [C.c_int]
+        L.srmhd_mlp_cache_bytes.restype = C.c_size_t
+        L.srmhd_mlp_quantize.argtypes = [_VP, _VP, C.c_int, _VP]
+        L.srmhd_mlp_forward.argtypes = [_VP, _VP, _VP, _VP, _VP, C.c_int, _VP]
+        L.srmhd_mlp_loss_grad.argtypes = [_VP, _VP, _VP, _VP, C.c_int, _VP]
+        L.srmhd_mlp_backward.argtypes = [_VP, _VP, _VP, C.c_int, _VP]
+        L.srmhd_mlp_adam.argtypes = [_VP, _VP, _VP, _VP, _VP, C.c_int, C.c_float, C.c_float,
+                                     C.c_float, C.c_float, C.c_int, _VP]
         L.srmhd_kernel_timing.argtypes = [_CTX, C.c_int]
         L.srmhd_get_kernel_times.argtypes = [_CTX, C.POINTER(C.c_double), C.POINTER(C.c_long)]
         L.srmhd_last_error.argtypes = [_CTX]
@@ -182,6 +194,58 @@ def srmhd_get_time(ctx):
 
 def srmhd_set_time(ctx, t, step):
     _check(lib().srmhd_set_time(ctx, float(t), int(step)), ctx)
+
+
+MLP_NPARAM = 4674
+MLP_OFF = {"W1": 0, "b1": 320, "W2": 384, "b2": 4480, "W3": 4544, "b3": 4672}
+
+
+def _vp(x):
+    return _VP(int(x) or None)
+
+
+def srmhd_set_mlp(ctx, params, w_bf16, norm):
+    arr = (C.c_float * 14)(*[float(v) for v in norm])
+    _check(lib().srmhd_set_mlp(ctx, _vp(params), _vp(w_bf16), arr), ctx)
+
+
+def srmhd_set_guess(ctx, guess):
+    _check(lib().srmhd_set_guess(ctx, int(guess)), ctx)
+
+
+def srmhd_harvest(ctx, feats, targets, cap, frac, seed):
+    n = C.c_int()
+    _check(lib().srmhd_harvest(ctx, _vp(feats), _vp(targets), int(cap), float(frac),
+                               int(seed), C.byref(n)), ctx)
+    return n.value
+
+
+def srmhd_mlp_cache_bytes(batch):
+    return lib().srmhd_mlp_cache_bytes(int(batch))
+
+
+def srmhd_mlp_quantize(params, w_bf16, n, stream=0):
+    _check(lib().srmhd_mlp_quantize(_vp(params), _vp(w_bf16), int(n), _vp(stream)))
+
+
+def srmhd_mlp_forward(params, w_bf16, x, y, cache, batch, stream=0):
+    _check(lib().srmhd_mlp_forward(_vp(params), _vp(w_bf16), _vp(x), _vp(y), _vp(cache),
+                                   int(batch), _vp(stream)))
+
+
+def srmhd_mlp_loss_grad(y, t, cache, loss, batch, stream=0):
+    _check(lib().srmhd_mlp_loss_grad(_vp(y), _vp(t), _vp(cache), _vp(loss), int(batch),
+                                     _vp(stream)))
+
+
+def srmhd_mlp_backward(w_bf16, cache, grad, batch, stream=0):
+    _check(lib().srmhd_mlp_backward(_vp(w_bf16), _vp(cache), _vp(grad), int(batch), _vp(stream)))
+
+
+def srmhd_mlp_adam(params, w_bf16, m, v, grad, n, lr, beta1, beta2, eps, t, stream=0):
+    _check(lib().srmhd_mlp_adam(_vp(params), _vp(w_bf16), _vp(m), _vp(v), _vp(grad), int(n),
+                                float(lr), float(beta1), float(beta2), float(eps), int(t),
+                                _vp(stream)))
 
 
 NKCLASS = 9

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsrmhd.so")
-SOURCES = ["srmhd_kernels.hip", "srmhd_api.hip"]
+SOURCES = ["srmhd_kernels.hip", "srmhd_api.hip", "srmhd_mlp.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

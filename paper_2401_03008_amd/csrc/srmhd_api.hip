@@ -42,6 +42,9 @@ struct srmhd_ctx {
   int ev_used;
   double kms[SRMHD_NKCLASS];
   long kcount[SRMHD_NKCLASS];
+  // learned guess
+  bool mlp_set;
+  MlpDev mlp;
 };
 
 static std::string g_create_error;
@@ -110,7 +113,6 @@ std::string validate(const srmhd_config* c) {
   if (c->precision != SRMHD_FP64 && c->precision != SRMHD_MIXED) return "bad precision";
   if (c->guess != SRMHD_GUESS_PREV && c->guess != SRMHD_GUESS_COLD && c->guess != SRMHD_GUESS_MLP)
     return "bad guess mode";
-  if (c->guess == SRMHD_GUESS_MLP) return "learned guess is not available in this build";
   if (c->newton_maxit < 1 || c->newton_maxit > 1000) return "newton_maxit must be in 1..1000";
   if (!(c->newton_tol > 0.0 && c->newton_tol < 1e-3)) return "newton_tol must be in (0, 1e-3)";
   if (!(c->pfloor >= 0.0 && c->pfloor < 1.0)) return "pfloor must be in [0, 1)";
@@ -220,6 +222,7 @@ void launch_c2p_into(srmhd_ctx* c, double* const* prim64, float* const* prim32, 
   a.pfloor = c->cfg.pfloor;
   a.maxit = c->cfg.newton_maxit;
   a.guess = guess;
+  a.mlp = c->mlp;
   a.counters = c->counters;
   a.err = &c->sc->err;
   KTimer kt(c, 0);
@@ -227,8 +230,12 @@ void launch_c2p_into(srmhd_ctx* c, double* const* prim64, float* const* prim32, 
 }
 
 // One RK stage (1..3), or stage 0 = L(U) into rhs_out.
+int guess_code(const srmhd_ctx* c) {
+  return c->cfg.guess == SRMHD_GUESS_COLD ? 2 : (c->cfg.guess == SRMHD_GUESS_MLP ? 1 : 0);
+}
+
 void run_stage(srmhd_ctx* c, int stage, double* const* rhs_out) {
-  const int guess = c->cfg.guess == SRMHD_GUESS_COLD ? 2 : 0;
+  const int guess = guess_code(c);
   if (c->mixed)
     launch_c2p_into(c, nullptr, c->prim32, guess);
   else
@@ -318,6 +325,8 @@ int srmhd_create(const srmhd_config* cfg, const srmhd_buffers* buf, void* stream
   c->initialized = false;
   c->timing = false;
   c->ev_used = 0;
+  c->mlp_set = false;
+  std::memset(&c->mlp, 0, sizeof(c->mlp));
   for (int k = 0; k < SRMHD_NKCLASS; ++k) {
     c->kms[k] = 0.0;
     c->kcount[k] = 0;
@@ -386,6 +395,8 @@ int srmhd_step(srmhd_ctx* c, int nsteps) {
   if (!c) return SRMHD_E_INVAL;
   if (!c->initialized) return fail(c, SRMHD_E_STATE, "step before init_from_prims");
   if (nsteps < 0) return fail(c, SRMHD_E_INVAL, "nsteps < 0");
+  if (c->cfg.guess == SRMHD_GUESS_MLP && !c->mlp_set)
+    return fail(c, SRMHD_E_STATE, "learned guess selected but no network set");
   for (int s = 0; s < nsteps; ++s) {
     run_stage(c, 1, nullptr);
     run_stage(c, 2, nullptr);
@@ -398,6 +409,8 @@ int srmhd_rhs(srmhd_ctx* c, double* const rhs[8], double* amax_dev) {
   if (!c) return SRMHD_E_INVAL;
   if (!c->initialized) return fail(c, SRMHD_E_STATE, "rhs before init_from_prims");
   if (!rhs || !amax_dev) return fail(c, SRMHD_E_INVAL, "rhs/amax is NULL");
+  if (c->cfg.guess == SRMHD_GUESS_MLP && !c->mlp_set)
+    return fail(c, SRMHD_E_STATE, "learned guess selected but no network set");
   for (int n = 0; n < 8; ++n)
     if (!rhs[n]) return fail(c, SRMHD_E_INVAL, "rhs entry is NULL");
   // the running CFL maximum belongs to the step sequence: clear, use, clear
@@ -413,7 +426,9 @@ int srmhd_get_primitives(srmhd_ctx* c, double* const prim[8]) {
   if (!prim) return fail(c, SRMHD_E_INVAL, "prim is NULL");
   for (int n = 0; n < 8; ++n)
     if (!prim[n]) return fail(c, SRMHD_E_INVAL, "prim entry is NULL");
-  launch_c2p_into(c, prim, nullptr, c->cfg.guess == SRMHD_GUESS_COLD ? 2 : 0);
+  if (c->cfg.guess == SRMHD_GUESS_MLP && !c->mlp_set)
+    return fail(c, SRMHD_E_STATE, "learned guess selected but no network set");
+  launch_c2p_into(c, prim, nullptr, guess_code(c));
   return check_launch(c, "get_primitives");
 }
 
@@ -498,6 +513,74 @@ int srmhd_set_time(srmhd_ctx* c, double t, long step) {
   if (!std::isfinite(t) || step < 0) return fail(c, SRMHD_E_INVAL, "bad time or step");
   launch_set_time(c->sc, t, step, c->stream);
   return check_launch(c, "set_time");
+}
+
+int srmhd_set_mlp(srmhd_ctx* c, const float* params, const uint16_t* w_bf16, const float* norm) {
+  if (!c) return SRMHD_E_INVAL;
+  if (!params || !w_bf16 || !norm) return fail(c, SRMHD_E_INVAL, "params/w_bf16/norm is NULL");
+  MlpDev m;
+  m.w = w_bf16;
+  m.p = params;
+  for (int k = 0; k < kMlpIn; ++k) {
+    if (!(norm[kMlpIn + k] > 0.f) || !std::isfinite(norm[k]))
+      return fail(c, SRMHD_E_INVAL, "feature std must be > 0 and means finite");
+    m.fmean[k] = norm[k];
+    m.finv[k] = 1.f / norm[kMlpIn + k];
+  }
+  for (int k = 0; k < kMlpOut; ++k) {
+    if (!(norm[2 * kMlpIn + kMlpOut + k] > 0.f) || !std::isfinite(norm[2 * kMlpIn + k]))
+      return fail(c, SRMHD_E_INVAL, "output std must be > 0 and means finite");
+    m.omean[k] = norm[2 * kMlpIn + k];
+    m.ostd[k] = norm[2 * kMlpIn + kMlpOut + k];
+  }
+  c->mlp = m;
+  c->mlp_set = true;
+  return SRMHD_OK;
+}
+
+int srmhd_set_guess(srmhd_ctx* c, int guess) {
+  if (!c) return SRMHD_E_INVAL;
+  if (guess != SRMHD_GUESS_PREV && guess != SRMHD_GUESS_COLD && guess != SRMHD_GUESS_MLP)
+    return fail(c, SRMHD_E_INVAL, "bad guess mode");
+  if (guess == SRMHD_GUESS_MLP && !c->mlp_set)
+    return fail(c, SRMHD_E_STATE, "learned guess needs srmhd_set_mlp first");
+  c->cfg.guess = guess;
+  return SRMHD_OK;
+}
+
+int srmhd_harvest(srmhd_ctx* c, float* feats, float* targets, int cap, double frac, unsigned seed,
+                  int* n_out) {
+  if (!c) return SRMHD_E_INVAL;
+  if (!c->initialized) return fail(c, SRMHD_E_STATE, "harvest before init_from_prims");
+  if (!feats || !targets || !n_out || cap <= 0 || !(frac > 0.0 && frac <= 1.0))
+    return fail(c, SRMHD_E_INVAL, "bad harvest arguments");
+  HarvestArgs a;
+  a.g = c->g;
+  for (int n = 0; n < 5; ++n) a.cons[n] = c->buf.cons[n];
+  for (int d = 0; d < 3; ++d) a.bf[d] = c->buf.bface[d];
+  a.W = c->buf.guess_w;
+  a.gam = c->cfg.gamma_ad;
+  a.tol = c->cfg.newton_tol;
+  a.maxit = c->cfg.newton_maxit;
+  a.feats = feats;
+  a.targets = targets;
+  a.cap = cap;
+  // slot counter: the low 32 bits of the scalars block's harvest word
+  a.count = (unsigned int*)&c->sc->harvest;
+  launch_zero_u64(&c->sc->harvest, 1, c->stream);
+  a.frac = frac;
+  a.seed = seed;
+  launch_harvest(a, c->stream);
+  int rc = check_launch(c, "harvest");
+  if (rc != SRMHD_OK) return rc;
+  unsigned cnt = 0;
+  rc = hip_check(c, hipMemcpyAsync(&cnt, a.count, sizeof(unsigned), hipMemcpyDeviceToHost,
+                                   c->stream), "copy harvest count");
+  if (rc != SRMHD_OK) return rc;
+  rc = hip_check(c, hipStreamSynchronize(c->stream), "stream sync");
+  if (rc != SRMHD_OK) return rc;
+  *n_out = (int)(cnt < (unsigned)cap ? cnt : (unsigned)cap);
+  return SRMHD_OK;
 }
 
 int srmhd_kernel_timing(srmhd_ctx* c, int enable) {

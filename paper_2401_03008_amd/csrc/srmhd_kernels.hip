@@ -160,10 +160,11 @@ __device__ __forceinline__ bool c2p_usable(const C2PIn& q, double W) {
   return W > 0.0 && c2p_v2(q, W) < 1.0;
 }
 
-// returns 0 converged, 1 maxit reached, 2 unusable input, 3 p <= 0 (no floor)
+// returns 0 converged, 1 maxit reached, 2 unusable input, 3 p <= 0 (no floor),
+// 4 unusable guess with `strict` set (no iteration done)
 __device__ int con2prim(const double* u, double bx, double by, double bz, double gam,
                         double& Wio, int maxit, double tol, double pfloor, double* pr,
-                        int& iters, bool& floored) {
+                        int& iters, bool& floored, bool strict = false) {
   iters = 0;
   floored = false;
   bool finite = true;
@@ -181,6 +182,7 @@ __device__ int con2prim(const double* u, double bx, double by, double bz, double
 
   double w = Wio;
   if (!(isfinite(w) && c2p_usable(q, w))) {
+    if (strict) return 4;
     w = q.U;
     for (int n = 0; n < 200 && !c2p_usable(q, w); ++n) w *= 2.0;
   }
@@ -229,22 +231,65 @@ __device__ int con2prim(const double* u, double bx, double by, double bz, double
   return 0;
 }
 
-template <bool STATS>
+// Guess: the previous W (mode 0), a cold start from U (mode 2), or the
+// learned guess (mode 1): the network's (log(p/D), log Gamma) gives
+// W0 = D Gamma + g/(g-1) p Gamma^2; if Newton from W0 does not converge, or W0
+// is unusable, the inversion is redone from the previous W and counted.
+template <bool STATS, bool MLP>
 __global__ __launch_bounds__(kThreads) void k_c2p(C2PArgs a) {
   __shared__ unsigned s_cnt[CNT_N];
+  __shared__ uint16_t s_lx[MLP ? kBlockY * 64 * 16 : 1];
+  __shared__ float s_ly[MLP ? kBlockY * 128 : 1];
   BlockCounters bc;
   if (STATS) bc.init(s_cnt);
   const Cell c = cell_of(a.g);
-  int iters = 0, rc = 0;
+  int iters = 0, rc = 0, mlpfb = 0;
   bool floored = false;
+  double u[5] = {1.0, 0.0, 0.0, 0.0, 1.0};
+  double b[3] = {0.0, 0.0, 0.0};
+  double Wprev = 1.0;
   if (c.valid) {
-    double u[5];
     for (int n = 0; n < 5; ++n) u[n] = a.cons[n][c.id];
-    double b[3];
     for (int d = 0; d < 3; ++d) b[d] = 0.5 * (a.bf[d][minus1(a.g, c, d)] + a.bf[d][c.id]);
-    double W = a.guess == 2 ? -1.0 : a.W[c.id];
-    double pr[5];
+    Wprev = a.guess == 2 ? -1.0 : a.W[c.id];
+  }
+  double pr[5];
+  double W = Wprev;
+  if (MLP) {
+    const double S2 = u[1] * u[1] + u[2] * u[2] + u[3] * u[3];
+    const double B2 = b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
+    const double tau = u[1] * b[0] + u[2] * b[1] + u[3] * b[2];
+    double fd[kMlpIn];
+    mlp_features(u[0], S2, B2, tau, u[4], fd);
+    float fe[kMlpIn];
+    bool fin = true;
+    for (int k = 0; k < kMlpIn; ++k) {
+      fe[k] = (float)fd[k];
+      fin = fin && isfinite(fe[k]);
+    }
+    if (!fin)
+      for (int k = 0; k < kMlpIn; ++k) fe[k] = 0.f;
+    float out[kMlpOut];
+    mlp_wave(a.mlp, fe, &s_lx[threadIdx.y * 64 * 16], &s_ly[threadIdx.y * 128], out,
+             []() { __syncthreads(); });
+    const double lor = exp(fmax((double)out[1], 0.0));
+    const double pg = u[0] * exp((double)out[0]);
+    W = fin ? u[0] * lor + a.gam / (a.gam - 1.0) * pg * lor * lor : -1.0;
+    if (c.valid) {
+      rc = con2prim(u, b[0], b[1], b[2], a.gam, W, a.maxit, a.tol, a.pfloor, pr, iters, floored,
+                    true);
+      if (rc == 1 || rc == 4) {
+        int it2 = 0;
+        W = Wprev;
+        rc = con2prim(u, b[0], b[1], b[2], a.gam, W, a.maxit, a.tol, a.pfloor, pr, it2, floored);
+        iters += it2;
+        mlpfb = 1;
+      }
+    }
+  } else if (c.valid) {
     rc = con2prim(u, b[0], b[1], b[2], a.gam, W, a.maxit, a.tol, a.pfloor, pr, iters, floored);
+  }
+  if (c.valid) {
     a.W[c.id] = W;
     if (a.prim64[0]) {
       for (int n = 0; n < 5; ++n) a.prim64[n][c.id] = pr[n];
@@ -264,6 +309,7 @@ __global__ __launch_bounds__(kThreads) void k_c2p(C2PArgs a) {
     bc.add_uniform(CNT_CALLS, c.valid ? 1u : 0u);
     bc.add_uniform(CNT_FAIL, (c.valid && rc != 0) ? 1u : 0u);
     bc.add_uniform(CNT_FLOOR, (c.valid && floored) ? 1u : 0u);
+    if (MLP) bc.add_uniform(CNT_MLPFB, (c.valid && mlpfb) ? 1u : 0u);
     bc.add_hist(CNT_HIST0, c.valid, iters < 31 ? iters : 31);
     bc.flush(a.counters);
   }
@@ -271,10 +317,59 @@ __global__ __launch_bounds__(kThreads) void k_c2p(C2PArgs a) {
 
 void launch_c2p(const C2PArgs& a, bool stats, hipStream_t s) {
   dim3 grid((a.g.nx + kBlockX - 1) / kBlockX, (a.g.ny + kBlockY - 1) / kBlockY, a.g.nz);
-  if (stats)
-    hipLaunchKernelGGL(k_c2p<true>, grid, dim3(kBlockX, kBlockY), 0, s, a);
-  else
-    hipLaunchKernelGGL(k_c2p<false>, grid, dim3(kBlockX, kBlockY), 0, s, a);
+  dim3 blk(kBlockX, kBlockY);
+  const bool mlp = a.guess == 1;
+  if (stats) {
+    if (mlp) hipLaunchKernelGGL((k_c2p<true, true>), grid, blk, 0, s, a);
+    else hipLaunchKernelGGL((k_c2p<true, false>), grid, blk, 0, s, a);
+  } else {
+    if (mlp) hipLaunchKernelGGL((k_c2p<false, true>), grid, blk, 0, s, a);
+    else hipLaunchKernelGGL((k_c2p<false, false>), grid, blk, 0, s, a);
+  }
+}
+
+// Training pairs from the current state: cells kept with probability frac
+// (counter-based hash of the cell index and seed), inverted from the stored
+// W (not written back); features as in the learned guess, targets
+// (log(p/D), log Gamma) of the converged primitives.
+__device__ __forceinline__ unsigned hash_u32(unsigned x, unsigned seed) {
+  x ^= seed * 0x9E3779B9u;
+  x ^= x >> 16;
+  x *= 0x85EBCA6Bu;
+  x ^= x >> 13;
+  x *= 0xC2B2AE35u;
+  x ^= x >> 16;
+  return x;
+}
+
+__global__ __launch_bounds__(kThreads) void k_harvest(HarvestArgs a) {
+  const Cell c = cell_of(a.g);
+  if (!c.valid) return;
+  const double r = hash_u32((unsigned)c.id, a.seed) * (1.0 / 4294967296.0);
+  if (!(r < a.frac)) return;
+  double u[5], b[3], pr[5];
+  for (int n = 0; n < 5; ++n) u[n] = a.cons[n][c.id];
+  for (int d = 0; d < 3; ++d) b[d] = 0.5 * (a.bf[d][minus1(a.g, c, d)] + a.bf[d][c.id]);
+  double W = a.W[c.id];
+  int it = 0;
+  bool fl = false;
+  const int rc = con2prim(u, b[0], b[1], b[2], a.gam, W, a.maxit, a.tol, 0.0, pr, it, fl);
+  if (rc != 0) return;
+  const double S2 = u[1] * u[1] + u[2] * u[2] + u[3] * u[3];
+  const double B2 = b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
+  const double tau = u[1] * b[0] + u[2] * b[1] + u[3] * b[2];
+  double f[kMlpIn];
+  mlp_features(u[0], S2, B2, tau, u[4], f);
+  const unsigned slot = atomicAdd(a.count, 1u);
+  if ((int)slot >= a.cap) return;
+  for (int k = 0; k < kMlpIn; ++k) a.feats[(size_t)slot * kMlpIn + k] = (float)f[k];
+  a.targets[(size_t)slot * kMlpOut + 0] = (float)log(pr[4] / u[0]);
+  a.targets[(size_t)slot * kMlpOut + 1] = (float)log(u[0] / pr[0]);
+}
+
+void launch_harvest(const HarvestArgs& a, hipStream_t s) {
+  dim3 grid((a.g.nx + kBlockX - 1) / kBlockX, (a.g.ny + kBlockY - 1) / kBlockY, a.g.nz);
+  hipLaunchKernelGGL(k_harvest, grid, dim3(kBlockX, kBlockY), 0, s, a);
 }
 
 // ------------------------------------------------ REC + face physics + HLL

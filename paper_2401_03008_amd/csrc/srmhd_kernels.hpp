@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "srmhd_mlp.hpp"
+
 namespace srmhd {
 
 constexpr int kBlockX = 64;  // one wavefront along x
@@ -35,6 +37,7 @@ struct DevScalars {
   unsigned int err;
   unsigned int pad;
   double reduce_out[16];  // diagnostics results
+  unsigned long long harvest;  // slot counter of the training-pair harvest
 };
 
 struct GridDims {
@@ -51,9 +54,25 @@ struct C2PArgs {
   float* prim32[8];   // FP32 copies for the mixed form (or null)
   double gam, tol, pfloor;
   int maxit;
-  int guess;  // 0 = previous W, 2 = cold start
+  int guess;  // 0 = previous W, 1 = learned guess (fallback previous W), 2 = cold start
+  MlpDev mlp;
   unsigned long long* counters;
   unsigned int* err;
+};
+
+struct HarvestArgs {
+  GridDims g;
+  const double* cons[5];
+  const double* bf[3];
+  const double* W;
+  double gam, tol;
+  int maxit;
+  float* feats;    // cap x 5
+  float* targets;  // cap x 2
+  int cap;
+  unsigned int* count;
+  double frac;
+  unsigned int seed;
 };
 
 template <typename TS>
@@ -118,6 +137,7 @@ struct ReduceArgs {
 // Launchers (srmhd_kernels.hip).  All asynchronous on `stream`.
 void launch_init(const InitArgs& a, hipStream_t s);
 void launch_c2p(const C2PArgs& a, bool stats, hipStream_t s);
+void launch_harvest(const HarvestArgs& a, hipStream_t s);
 template <typename TS>
 void launch_flux(int dir, const FluxArgs<TS>& a, bool cfl, bool stats, hipStream_t s);
 template <typename TS>

@@ -107,7 +107,7 @@ def cpa(n, diagonal=True, t=0.0, rho=1.0, p=1.0, B0=1.0, eta=1.0, gam=GAMMA_AD,
 
 
 def turbulence(n, sigma0=10.0, beta0=0.1, B0=1.0, nmodes=16, kmax=2, gamma_max=5.0,
-               seed=20240103, L=(1.0, 1.0, 1.0)):
+               seed=20240103, L=(1.0, 1.0, 1.0), device=None):
     """Decaying Alfvenic turbulence, 3D synthetic stand-in for the paper's 2D
     random-phase set-up (Sec. 5): uniform B0 along z, rho0 = B0^2/sigma0,
     p0 = beta0 B0^2 / 2, plus nmodes random-phase transverse modes with
@@ -121,7 +121,8 @@ def turbulence(n, sigma0=10.0, beta0=0.1, B0=1.0, nmodes=16, kmax=2, gamma_max=5
     cos(k.x + phi_v), e_k = (k_hat x z)/|k_hat x z|, rescaled so that
     max Gamma = gamma_max, v = u / sqrt(1 + u^2).
 
-    Returns (prim5, bf)."""
+    Returns (prim5, bf): numpy arrays, or torch float64 tensors on `device`.
+    The modes and phases come from numpy's default_rng(seed) either way."""
     nx, ny, nz = (n, n, n) if np.isscalar(n) else n
     rng = np.random.default_rng(seed)
     cand = []
@@ -135,44 +136,59 @@ def turbulence(n, sigma0=10.0, beta0=0.1, B0=1.0, nmodes=16, kmax=2, gamma_max=5
     phiB = rng.uniform(0, 2 * math.pi, nmodes)
     phiv = rng.uniform(0, 2 * math.pi, nmodes)
 
+    if device is None:
+        xp = np
+        ar = lambda m, o, h: (np.arange(m) + o) * h
+        mesh = lambda a, b, c: np.meshgrid(a, b, c, indexing="ij")
+        zeros = lambda: np.zeros((nz, ny, nx))
+        full = lambda v: np.full((nz, ny, nx), float(v))
+        roll = lambda a, ax: np.roll(a, 1, axis=ax)
+        cont = np.ascontiguousarray
+        amax = lambda a: float(a.max())
+    else:
+        import torch
+        xp = torch
+        ar = lambda m, o, h: (torch.arange(m, dtype=torch.float64, device=device) + o) * h
+        mesh = lambda a, b, c: torch.meshgrid(a, b, c, indexing="ij")
+        zeros = lambda: torch.zeros((nz, ny, nx), dtype=torch.float64, device=device)
+        full = lambda v: torch.full((nz, ny, nx), float(v), dtype=torch.float64, device=device)
+        roll = lambda a, ax: torch.roll(a, 1, dims=ax)
+        cont = lambda a: a.contiguous()
+        amax = lambda a: float(a.max().item())
     dx, dy, dz = L[0] / nx, L[1] / ny, L[2] / nz
-    xc = (np.arange(nx) + 0.5) * dx
-    yc = (np.arange(ny) + 0.5) * dy
-    zc = (np.arange(nz) + 0.5) * dz
-    xf, yf = (np.arange(nx) + 1.0) * dx, (np.arange(ny) + 1.0) * dy
-    shape = (nz, ny, nx)
+    xc, yc, zc = ar(nx, 0.5, dx), ar(ny, 0.5, dy), ar(nz, 0.5, dz)
+    xf, yf = ar(nx, 1.0, dx), ar(ny, 1.0, dy)
 
-    A = np.zeros(shape)
-    ux, uy = np.zeros(shape), np.zeros(shape)
-    Ze, Ye, Xe = np.meshgrid(zc, yf, xf, indexing="ij")
-    Zc, Yc, Xc = np.meshgrid(zc, yc, xc, indexing="ij")
+    A = zeros()
+    ux, uy = zeros(), zeros()
+    Ze, Ye, Xe = mesh(zc, yf, xf)
+    Zc, Yc, Xc = mesh(zc, yc, xc)
     for (a, b, c), pB, pv in zip(modes, phiB, phiv):
-        k = np.array([2 * math.pi * a / L[0], 2 * math.pi * b / L[1], 2 * math.pi * c / L[2]])
+        k = [2 * math.pi * a / L[0], 2 * math.pi * b / L[1], 2 * math.pi * c / L[2]]
         kp = math.hypot(k[0], k[1])
-        A += np.sin(k[0] * Xe + k[1] * Ye + k[2] * Ze + pB) / kp
-        kn = np.linalg.norm(k)
-        e = np.array([k[1], -k[0]]) / kn
-        e /= np.linalg.norm(e)
-        cv = np.cos(k[0] * Xc + k[1] * Yc + k[2] * Zc + pv)
+        A += xp.sin(k[0] * Xe + k[1] * Ye + k[2] * Ze + float(pB)) / kp
+        e = (k[1] / kp, -k[0] / kp)
+        cv = xp.cos(k[0] * Xc + k[1] * Yc + k[2] * Zc + float(pv))
         ux -= e[0] * cv
         uy -= e[1] * cv
+    del Ze, Ye, Xe, Zc, Yc, Xc
     # face B from the discrete curl of A_z (A at (i+1/2, j+1/2, k))
-    bx = (A - np.roll(A, 1, axis=1)) / dy
-    by = -(A - np.roll(A, 1, axis=2)) / dx
+    bx = (A - roll(A, 1)) / dy
+    by = -(A - roll(A, 2)) / dx
+    del A
     # rescale so that max |dB| at cell centres (face averages) equals B0
-    bxc = 0.5 * (bx + np.roll(bx, 1, axis=2))
-    byc = 0.5 * (by + np.roll(by, 1, axis=1))
-    scale = B0 / np.sqrt(bxc ** 2 + byc ** 2).max()
-    bx *= scale
-    by *= scale
-    bz = np.full(shape, B0)
+    bxc = 0.5 * (bx + roll(bx, 2))
+    byc = 0.5 * (by + roll(by, 1))
+    scale = B0 / math.sqrt(amax(bxc ** 2 + byc ** 2))
+    del bxc, byc
+    bx = bx * scale
+    by = by * scale
     umax = math.sqrt(gamma_max ** 2 - 1.0)
-    us = umax / np.sqrt(ux ** 2 + uy ** 2).max()
-    ux *= us
-    uy *= us
-    lor = np.sqrt(1.0 + ux ** 2 + uy ** 2)
+    us = umax / math.sqrt(amax(ux ** 2 + uy ** 2))
+    ux = ux * us
+    uy = uy * us
+    lor = xp.sqrt(1.0 + ux ** 2 + uy ** 2)
     rho0 = B0 * B0 / sigma0
     p0 = 0.5 * beta0 * B0 * B0
-    prim5 = [np.full(shape, rho0), ux / lor, uy / lor, np.zeros(shape), np.full(shape, p0)]
-    prim5 = [np.ascontiguousarray(a) for a in prim5]
-    return prim5, [np.ascontiguousarray(bx), np.ascontiguousarray(by), bz]
+    prim5 = [full(rho0), cont(ux / lor), cont(uy / lor), zeros(), full(p0)]
+    return prim5, [cont(bx), cont(by), full(B0)]

@@ -99,6 +99,21 @@ class Solver:
     def reset_counters(self):
         B.srmhd_reset_counters(self.ctx)
 
+    def set_mlp(self, mlp):
+        """Use a trained learned.Mlp for the Newton guess (kept by reference)."""
+        self._mlp = mlp
+        B.srmhd_set_mlp(self.ctx, mlp.params.data_ptr(), mlp.w.data_ptr(), mlp.norm)
+
+    def set_guess(self, guess):
+        B.srmhd_set_guess(self.ctx, _GUESS[guess])
+
+    def harvest(self, cap, frac, seed=1):
+        """(features (n, 5), targets (n, 2)) float32 device tensors."""
+        f = torch.empty((cap, 5), dtype=torch.float32, device=self.device)
+        t = torch.empty((cap, 2), dtype=torch.float32, device=self.device)
+        n = B.srmhd_harvest(self.ctx, f.data_ptr(), t.data_ptr(), cap, frac, seed)
+        return f[:n], t[:n]
+
     def kernel_timing(self, enable=True):
         B.srmhd_kernel_timing(self.ctx, enable)
 
