@@ -33,16 +33,15 @@ STEP_BYTES = 560.0          # algorithmic HBM bytes per cell-step of the state
 # face or edge) of each kernel, for the plain FP64 form and the mixed form.
 # Bytes: every array element the kernel must read or write, once.  Flops:
 # adds, multiplies, divides and square roots of the formulas (FMA = 2), MP5
-# counted on its limiter path (49 per call, 14 calls per face, 12 per edge).
+# counted on its limiter path (49 per call, 14 calls per face, 12 per edge;
+# the UCT kernel computes the three edges of a cell).
 KERNEL_UNITS = {
     # class: (bytes fp64, bytes mixed, flops per unit)
     "c2p": (144.0, 112.0, 200.0),
     "flux_x": (168.0, 88.0, 940.0),
     "flux_y": (168.0, 88.0, 940.0),
     "flux_z": (168.0, 88.0, 940.0),
-    "uct_x": (88.0, 64.0, 640.0),
-    "uct_y": (88.0, 64.0, 640.0),
-    "uct_z": (88.0, 64.0, 640.0),
+    "uct": (192.0, 120.0, 1920.0),
     "update": (336.0, 276.0, 80.0),
 }
 
@@ -65,8 +64,9 @@ def profiled_traffic(kernel_name):
     return None
 
 
-def run_form(n, precision, steps, warmup):
-    """Mcell-updates/s of one form on the diagonal CPA at n^3."""
+def run_form(n, precision, steps, warmup, mlp=None):
+    """Mcell-updates/s of one form on the diagonal CPA at n^3 (mlp: the
+    learned Newton guess), then Newton statistics over 2 more steps."""
     import torch
     from paper_2401_03008_amd import inputs
     from paper_2401_03008_amd.solver import Solver
@@ -74,6 +74,9 @@ def run_form(n, precision, steps, warmup):
     S = Solver(n, precision=precision, collect_stats=False)
     S.init(prim5, bf)
     del prim5, bf
+    if mlp is not None:
+        S.set_mlp(mlp)
+        S.set_guess("mlp")
     S.step(warmup)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -84,12 +87,25 @@ def run_form(n, precision, steps, warmup):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
     S.close()
-    del S
+    # Newton statistics of the same form (a separate run with counters on)
+    prim5, bf, _ = inputs.cpa(n, diagonal=True, device="cuda")
+    S2 = Solver(n, precision=precision, collect_stats=True)
+    S2.init(prim5, bf)
+    del prim5, bf
+    if mlp is not None:
+        S2.set_mlp(mlp)
+        S2.set_guess("mlp")
+    S2.step(2)
+    d = S2.diagnostics()
+    S2.close()
+    del S, S2
     torch.cuda.empty_cache()
     v = n ** 3 * steps / (ms / 1e3) / 1e6
     return {"cells": n ** 3, "steps": steps, "ms_per_step": round(ms / steps, 3),
             "Mcell_updates_per_s": round(v, 1),
-            "hbm_roofline_frac_step": round(v * 1e6 * STEP_BYTES / (HBM_PEAK_GBS * 1e9), 4)}
+            "hbm_roofline_frac_step": round(v * 1e6 * STEP_BYTES / (HBM_PEAK_GBS * 1e9), 4),
+            "newton_mean_iters": round(d["newton_iters"] / max(d["newton_calls"], 1), 3),
+            "mlp_fallback_rate": round(d["mlp_fallbacks"] / max(d["newton_calls"], 1), 5)}
 
 
 def cpu_baseline(seconds_target=15.0):
@@ -216,10 +232,21 @@ def main():
 
     forms = None
     if not args.no_forms:
+        from paper_2401_03008_amd.learned import train_default
         forms = {}
         for prec in ("fp64", "mixed"):
             print(f"[bench] form {prec} at {args.forms_n}^3", file=sys.stderr, flush=True)
             forms[prec] = run_form(args.forms_n, prec, max(5, args.steps // 2), 2)
+        print("[bench] training the learned guess", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        mlp, hist, npairs = train_default()
+        train_s = time.perf_counter() - t0
+        for prec in ("fp64", "mixed"):
+            key = f"{prec}+learned"
+            print(f"[bench] form {key} at {args.forms_n}^3", file=sys.stderr, flush=True)
+            forms[key] = run_form(args.forms_n, prec, max(5, args.steps // 2), 2, mlp=mlp)
+        forms["learned_training"] = {"pairs": npairs, "adam_steps": 1500, "batch": 4096,
+                                     "final_loss": hist[-1][1], "seconds": round(train_s, 2)}
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -249,7 +249,8 @@ def srmhd_mlp_adam(params, w_bf16, m, v, grad, n, lr, beta1, beta2, eps, t, stre
 
 
 NKCLASS = 9
-KCLASS_NAMES = ["c2p", "flux_x", "flux_y", "flux_z", "uct_x", "uct_y", "uct_z", "update", "dt"]
+KCLASS_NAMES = ["c2p", "flux_x", "flux_y", "flux_z", "uct", "uct_unused5", "uct_unused6",
+                "update", "dt"]
 
 
 def srmhd_kernel_timing(ctx, enable):

@@ -27,7 +27,7 @@ struct srmhd_ctx {
   DevScalars* sc;
   unsigned long long* counters;
   double* partial;
-  double* u0[8];
+  double* ureg[8];  // RK stage register (U1, then U2)
   double* prim64[8];
   float* prim32[8];
   void* fhat[3][5];
@@ -139,7 +139,7 @@ Layout layout_of(const srmhd_config* c) {
   L.arr_bytes64 = align_up(n * sizeof(double));
   L.arr_bytes32 = align_up(n * sizeof(float));
   const bool mixed = c->precision == SRMHD_MIXED;
-  // U0 (8) + edge E (3) always FP64; prims FP64 (8) or FP32 (8); faces
+  // RK register (8) + edge E (3) always FP64; prims FP64 (8) or FP32 (8); faces
   // (15 fluxes + 6 speeds + 18 velocity states) in the flux precision.
   L.n64 = 8 + 3 + (mixed ? 0 : 8 + 39);
   L.n32 = mixed ? 8 + 39 : 0;
@@ -147,15 +147,30 @@ Layout layout_of(const srmhd_config* c) {
   return L;
 }
 
+// The stage's input state: the caller's arrays (U^n) in stage 1 and for the
+// stand-alone operator, the work register (U1, U2) in stages 2 and 3.
+struct StageState {
+  const double* cons[5];
+  double* bf[3];
+};
+
+StageState stage_state(srmhd_ctx* c, int stage) {
+  StageState s;
+  const bool reg = stage == 2 || stage == 3;
+  for (int n = 0; n < 5; ++n) s.cons[n] = reg ? c->ureg[n] : c->buf.cons[n];
+  for (int d = 0; d < 3; ++d) s.bf[d] = reg ? c->ureg[5 + d] : c->buf.bface[d];
+  return s;
+}
+
 template <typename TS>
-void stage_flux(srmhd_ctx* c, bool cfl) {
+void stage_flux(srmhd_ctx* c, const StageState& st, bool cfl) {
   const bool stats = c->cfg.collect_stats != 0;
   for (int d = 0; d < 3; ++d) {
     FluxArgs<TS> a;
     a.g = c->g;
     for (int n = 0; n < 8; ++n)
       a.prim[n] = c->mixed ? (const TS*)c->prim32[n] : (const TS*)c->prim64[n];
-    a.bn = c->buf.bface[d];
+    a.bn = st.bf[d];
     for (int n = 0; n < 5; ++n) a.fhat[n] = (TS*)c->fhat[d][n];
     a.ap = (TS*)c->apm[d][0];
     a.am = (TS*)c->apm[d][1];
@@ -175,31 +190,32 @@ void stage_flux(srmhd_ctx* c, bool cfl) {
 }
 
 template <typename TS>
-void stage_uct_update(srmhd_ctx* c, int stage, double* const* rhs_out) {
-  for (int k = 0; k < 3; ++k) {
-    const int p = (k + 1) % 3, q = (k + 2) % 3;
-    UctArgs<TS> a;
+void stage_uct_update(srmhd_ctx* c, const StageState& st, int stage, double* const* rhs_out) {
+  {
+    Uct3Args<TS> a;
     a.g = c->g;
-    for (int n = 0; n < 6; ++n) a.fvp[n] = (const TS*)c->fv[p][n];
-    a.app = (const TS*)c->apm[p][0];
-    a.amp = (const TS*)c->apm[p][1];
-    a.apq = (const TS*)c->apm[q][0];
-    a.amq = (const TS*)c->apm[q][1];
-    a.bp = c->buf.bface[p];
-    a.bq = c->buf.bface[q];
-    a.e = c->edge[k];
-    KTimer kt(c, 4 + k);
-    launch_uct<TS>(k, a, c->stream);
+    for (int d = 0; d < 3; ++d) {
+      for (int n = 0; n < 6; ++n) a.fv[d][n] = (const TS*)c->fv[d][n];
+      a.ap[d] = (const TS*)c->apm[d][0];
+      a.am[d] = (const TS*)c->apm[d][1];
+      a.bf[d] = st.bf[d];
+      a.e[d] = c->edge[d];
+    }
+    KTimer kt(c, 4);
+    launch_uct3<TS>(a, c->stream);
   }
   UpdArgs<TS> u;
   u.g = c->g;
   for (int d = 0; d < 3; ++d)
     for (int n = 0; n < 5; ++n) u.fhat[d][n] = (const TS*)c->fhat[d][n];
   for (int k = 0; k < 3; ++k) u.e[k] = c->edge[k];
-  for (int n = 0; n < 5; ++n) u.u[n] = c->buf.cons[n];
-  for (int d = 0; d < 3; ++d) u.u[5 + d] = c->buf.bface[d];
+  double* state[8];
+  for (int n = 0; n < 5; ++n) state[n] = c->buf.cons[n];
+  for (int d = 0; d < 3; ++d) state[5 + d] = c->buf.bface[d];
   for (int n = 0; n < 8; ++n) {
-    u.u0[n] = c->u0[n];
+    u.ucur[n] = n < 5 ? st.cons[n] : st.bf[n - 5];
+    u.u0[n] = state[n];
+    u.uout[n] = stage == 3 ? state[n] : c->ureg[n];
     u.rhs_out[n] = rhs_out ? rhs_out[n] : nullptr;
   }
   u.sc = c->sc;
@@ -207,11 +223,12 @@ void stage_uct_update(srmhd_ctx* c, int stage, double* const* rhs_out) {
   launch_update<TS>(stage, u, c->stream);
 }
 
-void launch_c2p_into(srmhd_ctx* c, double* const* prim64, float* const* prim32, int guess) {
+void launch_c2p_into(srmhd_ctx* c, const StageState& st, double* const* prim64,
+                     float* const* prim32, int guess) {
   C2PArgs a;
   a.g = c->g;
-  for (int n = 0; n < 5; ++n) a.cons[n] = c->buf.cons[n];
-  for (int d = 0; d < 3; ++d) a.bf[d] = c->buf.bface[d];
+  for (int n = 0; n < 5; ++n) a.cons[n] = st.cons[n];
+  for (int d = 0; d < 3; ++d) a.bf[d] = st.bf[d];
   a.W = c->buf.guess_w;
   for (int n = 0; n < 8; ++n) {
     a.prim64[n] = prim64 ? prim64[n] : nullptr;
@@ -236,19 +253,20 @@ int guess_code(const srmhd_ctx* c) {
 
 void run_stage(srmhd_ctx* c, int stage, double* const* rhs_out) {
   const int guess = guess_code(c);
+  const StageState st = stage_state(c, stage);
   if (c->mixed)
-    launch_c2p_into(c, nullptr, c->prim32, guess);
+    launch_c2p_into(c, st, nullptr, c->prim32, guess);
   else
-    launch_c2p_into(c, c->prim64, nullptr, guess);
+    launch_c2p_into(c, st, c->prim64, nullptr, guess);
   const bool cfl = stage <= 1;
-  if (c->mixed) stage_flux<float>(c, cfl);
-  else stage_flux<double>(c, cfl);
+  if (c->mixed) stage_flux<float>(c, st, cfl);
+  else stage_flux<double>(c, st, cfl);
   if (stage == 1) {
     KTimer kt(c, 8);
     launch_dt(c->sc, c->cfg.cfl, c->cfg.dt_fixed, c->stream);
   }
-  if (c->mixed) stage_uct_update<float>(c, stage, rhs_out);
-  else stage_uct_update<double>(c, stage, rhs_out);
+  if (c->mixed) stage_uct_update<float>(c, st, stage, rhs_out);
+  else stage_uct_update<double>(c, st, stage, rhs_out);
 }
 
 __global__ void k_take_amax(srmhd::DevScalars* sc, double* out) {
@@ -339,7 +357,7 @@ int srmhd_create(const srmhd_config* cfg, const srmhd_buffers* buf, void* stream
   auto take64 = [&]() { double* r = (double*)p; p += L.arr_bytes64; return r; };
   auto take32 = [&]() { float* r = (float*)p; p += L.arr_bytes32; return r; };
   auto takeT = [&]() -> void* { return c->mixed ? (void*)take32() : (void*)take64(); };
-  for (int n = 0; n < 8; ++n) c->u0[n] = take64();
+  for (int n = 0; n < 8; ++n) c->ureg[n] = take64();
   for (int k = 0; k < 3; ++k) c->edge[k] = take64();
   for (int n = 0; n < 8; ++n) {
     c->prim64[n] = c->mixed ? nullptr : take64();
@@ -428,7 +446,7 @@ int srmhd_get_primitives(srmhd_ctx* c, double* const prim[8]) {
     if (!prim[n]) return fail(c, SRMHD_E_INVAL, "prim entry is NULL");
   if (c->cfg.guess == SRMHD_GUESS_MLP && !c->mlp_set)
     return fail(c, SRMHD_E_STATE, "learned guess selected but no network set");
-  launch_c2p_into(c, prim, nullptr, guess_code(c));
+  launch_c2p_into(c, stage_state(c, 0), prim, nullptr, guess_code(c));
   return check_launch(c, "get_primitives");
 }
 

@@ -23,18 +23,49 @@ struct Cell {
   bool valid;
 };
 
+// Tiles of 64 x 4 cells, launched as a 1D grid in x-fastest order.  (A remap
+// giving each of the 8 XCDs a contiguous slab of tiles -- workgroups go to the
+// XCDs round-robin -- measured 3-10% slower on the stencil kernels: eight
+// distant slabs then compete for the shared last-level cache, while the
+// natural order keeps all in-flight tiles within a few planes.)  Tiles past
+// the end of the padded grid have valid = false for the whole workgroup.
+constexpr int kXcds = 8;
+
+struct TileGrid {
+  int nbx, nby, ntiles;
+};
+
+__device__ __forceinline__ TileGrid tiles_of(const GridDims& g) {
+  TileGrid t;
+  t.nbx = (g.nx + kBlockX - 1) / kBlockX;
+  t.nby = (g.ny + kBlockY - 1) / kBlockY;
+  t.ntiles = t.nbx * t.nby * g.nz;
+  return t;
+}
+
+__device__ __forceinline__ int tile_index() { return blockIdx.x; }
+
 __device__ __forceinline__ Cell cell_of(const GridDims& g) {
+  const TileGrid t = tiles_of(g);
+  const int L = tile_index();
   Cell c;
-  c.i = blockIdx.x * kBlockX + threadIdx.x;
-  c.j = blockIdx.y * kBlockY + threadIdx.y;
-  c.k = blockIdx.z;
-  c.valid = c.i < g.nx && c.j < g.ny;
-  c.id = (c.k * g.ny + c.j) * g.nx + c.i;
+  const int bx = L % t.nbx, r = L / t.nbx;
+  const int by = r % t.nby, bz = r / t.nby;
+  c.i = bx * kBlockX + threadIdx.x;
+  c.j = by * kBlockY + threadIdx.y;
+  c.k = bz;
+  c.valid = L < t.ntiles && c.i < g.nx && c.j < g.ny;
+  c.id = c.valid ? (c.k * g.ny + c.j) * g.nx + c.i : 0;
   return c;
 }
 
-__device__ __forceinline__ int block_linear() {
-  return (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+__device__ __forceinline__ int block_linear() { return blockIdx.x; }
+
+// 1D launch grid covering every tile, padded to a multiple of the XCD count.
+inline dim3 cell_grid(const GridDims& g) {
+  const long long n = (long long)((g.nx + kBlockX - 1) / kBlockX) *
+                      ((g.ny + kBlockY - 1) / kBlockY) * g.nz;
+  return dim3((unsigned)((n + kXcds - 1) / kXcds * kXcds));
 }
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x; }
@@ -135,7 +166,7 @@ __global__ __launch_bounds__(kThreads) void k_init(InitArgs a) {
 }
 
 void launch_init(const InitArgs& a, hipStream_t s) {
-  dim3 grid((a.g.nx + kBlockX - 1) / kBlockX, (a.g.ny + kBlockY - 1) / kBlockY, a.g.nz);
+  const dim3 grid = cell_grid(a.g);
   hipLaunchKernelGGL(k_init, grid, dim3(kBlockX, kBlockY), 0, s, a);
 }
 
@@ -151,13 +182,20 @@ struct C2PIn {
   double D, U, S2, B2, tau2, gf;
 };
 
-__device__ __forceinline__ double c2p_v2(const C2PIn& q, double W) {
+// v^2(W), with 1/W and 1/(W + B^2) from one reciprocal (returned for reuse).
+__device__ __forceinline__ double c2p_v2(const C2PIn& q, double W, double& iw, double& iwb) {
   const double WB = W + q.B2;
-  return (q.S2 + q.tau2 * (2.0 * W + q.B2) / (W * W)) / (WB * WB);
+  const double r = 1.0 / (W * WB);
+  iw = WB * r;
+  iwb = W * r;
+  return (q.S2 + q.tau2 * (2.0 * W + q.B2) * iw * iw) * iwb * iwb;
 }
 
-__device__ __forceinline__ bool c2p_usable(const C2PIn& q, double W) {
-  return W > 0.0 && c2p_v2(q, W) < 1.0;
+__device__ __forceinline__ bool c2p_usable(const C2PIn& q, double W, double& v2, double& iw,
+                                           double& iwb) {
+  if (!(W > 0.0) || !isfinite(W)) return false;
+  v2 = c2p_v2(q, W, iw, iwb);
+  return v2 < 1.0;
 }
 
 // returns 0 converged, 1 maxit reached, 2 unusable input, 3 p <= 0 (no floor),
@@ -180,33 +218,46 @@ __device__ int con2prim(const double* u, double bx, double by, double bz, double
   q.gf = (gam - 1.0) / gam;
   if (!finite || !(q.D > 0.0) || !(q.U > 0.0)) return 2;
 
-  double w = Wio;
-  if (!(isfinite(w) && c2p_usable(q, w))) {
+  double w = Wio, v2 = 0.0, iw = 0.0, iwb = 0.0;
+  if (!c2p_usable(q, w, v2, iw, iwb)) {
     if (strict) return 4;
     w = q.U;
-    for (int n = 0; n < 200 && !c2p_usable(q, w); ++n) w *= 2.0;
+    for (int n = 0; n < 200 && !c2p_usable(q, w, v2, iw, iwb); ++n) w *= 2.0;
   }
   int it = 0;
   bool conv = false;
   while (it < maxit) {
     ++it;
-    const double v2 = c2p_v2(q, w);
-    const double sqv = sqrt(1.0 - v2);
-    const double p = q.gf * (w * (1.0 - v2) - q.D * sqv);
-    const double iw = 1.0 / w;
+    const double omv = 1.0 - v2;
+    const double sqv = sqrt(omv);
+    const double p = q.gf * (w * omv - q.D * sqv);
     const double tb = 0.5 * q.B2 * (1.0 + v2);
-    const double tt = 0.5 * q.tau2 * iw * iw;
+    const double iw2 = iw * iw;
+    const double tt = 0.5 * q.tau2 * iw2;
     const double f = w - p + tb - tt - q.U;
     const double fs = w + fabs(p) + tb + tt + q.U;
-    const double iwb = 1.0 / (w + q.B2);
-    const double dv2 = -2.0 * q.tau2 * iw * iw * iw * iwb - 2.0 * v2 * iwb;
-    const double dp = q.gf * ((1.0 - v2) - w * dv2 + 0.5 * q.D * dv2 / sqv);
-    const double fp = 1.0 - dp + 0.5 * q.B2 * dv2 + q.tau2 * iw * iw * iw;
+    const double tiw3 = q.tau2 * iw2 * iw;
+    const double dv2 = -2.0 * tiw3 * iwb - 2.0 * v2 * iwb;
+    // 1/sqrt(1 - v^2) only scales a term of f' (the step's convergence rate,
+    // not the root), so the hardware reciprocal square root suffices
+    const double isqv = __builtin_amdgcn_rsq(omv);
+    const double dp = q.gf * (omv - w * dv2 + 0.5 * q.D * dv2 * isqv);
+    const double fp = 1.0 - dp + 0.5 * q.B2 * dv2 + tiw3;
     double wn = w - f / fp;
-    for (int n = 0; n < 100 && !(isfinite(wn) && c2p_usable(q, wn)); ++n) wn = 0.5 * (wn + w);
-    if (!isfinite(wn)) wn = w;
+    double v2n = v2, iwn = iw, iwbn = iwb;
+    int n = 0;
+    for (; n < 100 && !c2p_usable(q, wn, v2n, iwn, iwbn); ++n) wn = 0.5 * (wn + w);
+    if (n == 100) {  // no usable point between the iterates: stay
+      wn = w;
+      v2n = v2;
+      iwn = iw;
+      iwbn = iwb;
+    }
     const double dw = wn - w;
     w = wn;
+    v2 = v2n;
+    iw = iwn;
+    iwb = iwbn;
     if (fabs(dw) <= fmax(tol * w, 8.0 * DBL_EPSILON * fs / fabs(fp))) {
       conv = true;
       break;
@@ -214,13 +265,12 @@ __device__ int con2prim(const double* u, double bx, double by, double bz, double
   }
   Wio = w;
   iters = it;
-  const double v2 = c2p_v2(q, w);
   const double sqv = sqrt(1.0 - v2);
-  const double aa = tau / w, den = 1.0 / (w + q.B2);
+  const double aa = tau * iw;
   pr[0] = q.D * sqv;
-  pr[1] = (u[1] + aa * bx) * den;
-  pr[2] = (u[2] + aa * by) * den;
-  pr[3] = (u[3] + aa * bz) * den;
+  pr[1] = (u[1] + aa * bx) * iwb;
+  pr[2] = (u[2] + aa * by) * iwb;
+  pr[3] = (u[3] + aa * bz) * iwb;
   pr[4] = q.gf * (w * (1.0 - v2) - q.D * sqv);
   if (pfloor > 0.0 && pr[4] < pfloor * pr[0]) {
     pr[4] = pfloor * pr[0];
@@ -316,7 +366,7 @@ __global__ __launch_bounds__(kThreads) void k_c2p(C2PArgs a) {
 }
 
 void launch_c2p(const C2PArgs& a, bool stats, hipStream_t s) {
-  dim3 grid((a.g.nx + kBlockX - 1) / kBlockX, (a.g.ny + kBlockY - 1) / kBlockY, a.g.nz);
+  const dim3 grid = cell_grid(a.g);
   dim3 blk(kBlockX, kBlockY);
   const bool mlp = a.guess == 1;
   if (stats) {
@@ -368,7 +418,7 @@ __global__ __launch_bounds__(kThreads) void k_harvest(HarvestArgs a) {
 }
 
 void launch_harvest(const HarvestArgs& a, hipStream_t s) {
-  dim3 grid((a.g.nx + kBlockX - 1) / kBlockX, (a.g.ny + kBlockY - 1) / kBlockY, a.g.nz);
+  const dim3 grid = cell_grid(a.g);
   hipLaunchKernelGGL(k_harvest, grid, dim3(kBlockX, kBlockY), 0, s, a);
 }
 
@@ -397,10 +447,7 @@ __global__ __launch_bounds__(kThreads) void k_flux(FluxArgs<TS> a) {
     stencil6(a.g, c, DIR, idx);
     FaceState<T> L, R;
     auto rec = [&](const TS* q, T& l, T& r) {
-      const T s0 = q[idx[0]], s1 = q[idx[1]], s2 = q[idx[2]], s3 = q[idx[3]], s4 = q[idx[4]],
-              s5 = q[idx[5]];
-      l = mp5<T>(s0, s1, s2, s3, s4);
-      r = mp5<T>(s5, s4, s3, s2, s1);
+      mp5_pair<T>(q[idx[0]], q[idx[1]], q[idx[2]], q[idx[3]], q[idx[4]], q[idx[5]], l, r);
     };
     rec(a.prim[0], L.rho, R.rho);
     rec(a.prim[1 + DIR], L.vn, R.vn);
@@ -487,7 +534,7 @@ __global__ __launch_bounds__(kThreads) void k_flux(FluxArgs<TS> a) {
 
 template <typename TS>
 void launch_flux(int dir, const FluxArgs<TS>& a, bool cfl, bool stats, hipStream_t s) {
-  dim3 grid((a.g.nx + kBlockX - 1) / kBlockX, (a.g.ny + kBlockY - 1) / kBlockY, a.g.nz);
+  const dim3 grid = cell_grid(a.g);
   dim3 blk(kBlockX, kBlockY);
 #define SRMHD_FLUX(D, C, S) hipLaunchKernelGGL((k_flux<D, TS, C, S>), grid, blk, 0, s, a)
   if (dir == 0) {
@@ -512,59 +559,67 @@ template void launch_flux<float>(int, const FluxArgs<float>&, bool, bool, hipStr
 // along Q to the edge (corner states ab), B_P (P faces) along Q, B_Q (Q faces)
 // along P; E^{ab} = v_Q^{ab} B_P^b - v_P^{ab} B_Q^a (E = -v x B); edge speeds
 // are the maxima over the two adjacent faces of each direction.
+// One thread computes E_x, E_y and E_z of its cell.
 template <int K, typename TS>
-__global__ __launch_bounds__(kThreads) void k_uct(UctArgs<TS> a) {
+__device__ __forceinline__ double uct_one(const Uct3Args<TS>& a, int id, const int* const* st) {
   constexpr int P = (K + 1) % 3, Q = (K + 2) % 3;
-  const Cell c = cell_of(a.g);
-  if (!c.valid) return;
-  int iq[6], ip[6];
-  stencil6(a.g, c, Q, iq);
-  stencil6(a.g, c, P, ip);
+  const int* iq = st[Q];
+  const int* ip = st[P];
   auto rec = [&](auto q, const int* idx, double& l, double& r) {
-    const double s0 = (double)q[idx[0]], s1 = (double)q[idx[1]], s2 = (double)q[idx[2]],
-                 s3 = (double)q[idx[3]], s4 = (double)q[idx[4]], s5 = (double)q[idx[5]];
-    l = mp5<double>(s0, s1, s2, s3, s4);
-    r = mp5<double>(s5, s4, s3, s2, s1);
+    mp5_pair<double>((double)q[idx[0]], (double)q[idx[1]], (double)q[idx[2]],
+                     (double)q[idx[3]], (double)q[idx[4]], (double)q[idx[5]], l, r);
   };
   double vp[2][2], vq[2][2];
 #pragma unroll
   for (int sd = 0; sd < 2; ++sd) {
-    rec(a.fvp[3 * sd + P], iq, vp[sd][0], vp[sd][1]);
-    rec(a.fvp[3 * sd + Q], iq, vq[sd][0], vq[sd][1]);
+    rec(a.fv[P][3 * sd + P], iq, vp[sd][0], vp[sd][1]);
+    rec(a.fv[P][3 * sd + Q], iq, vq[sd][0], vq[sd][1]);
   }
   double bpL, bpR, bqL, bqR;
-  rec(a.bp, iq, bpL, bpR);
-  rec(a.bq, ip, bqL, bqR);
-  const double app = fmax((double)a.app[c.id], (double)a.app[iq[3]]);
-  const double amp = fmax((double)a.amp[c.id], (double)a.amp[iq[3]]);
-  const double aqp = fmax((double)a.apq[c.id], (double)a.apq[ip[3]]);
-  const double aqm = fmax((double)a.amq[c.id], (double)a.amq[ip[3]]);
+  rec(a.bf[P], iq, bpL, bpR);
+  rec(a.bf[Q], ip, bqL, bqR);
+  const double app = fmax((double)a.ap[P][id], (double)a.ap[P][iq[3]]);
+  const double amp = fmax((double)a.am[P][id], (double)a.am[P][iq[3]]);
+  const double aqp = fmax((double)a.ap[Q][id], (double)a.ap[Q][ip[3]]);
+  const double aqm = fmax((double)a.am[Q][id], (double)a.am[Q][ip[3]]);
   double E[2][2];
 #pragma unroll
   for (int sa = 0; sa < 2; ++sa)
 #pragma unroll
     for (int sb = 0; sb < 2; ++sb)
       E[sa][sb] = vq[sa][sb] * (sb ? bpR : bpL) - vp[sa][sb] * (sa ? bqR : bqL);
-  a.e[c.id] = uct_edge<double>(E[0][0], E[0][1], E[1][0], E[1][1], app, amp, aqp, aqm, bqL, bqR,
-                               bpL, bpR);
+  return uct_edge<double>(E[0][0], E[0][1], E[1][0], E[1][1], app, amp, aqp, aqm, bqL, bqR,
+                          bpL, bpR);
 }
 
 template <typename TS>
-void launch_uct(int k, const UctArgs<TS>& a, hipStream_t s) {
-  dim3 grid((a.g.nx + kBlockX - 1) / kBlockX, (a.g.ny + kBlockY - 1) / kBlockY, a.g.nz);
-  dim3 blk(kBlockX, kBlockY);
-  if (k == 0) hipLaunchKernelGGL((k_uct<0, TS>), grid, blk, 0, s, a);
-  else if (k == 1) hipLaunchKernelGGL((k_uct<1, TS>), grid, blk, 0, s, a);
-  else hipLaunchKernelGGL((k_uct<2, TS>), grid, blk, 0, s, a);
+__global__ __launch_bounds__(kThreads) void k_uct3(Uct3Args<TS> a) {
+  const Cell c = cell_of(a.g);
+  if (!c.valid) return;
+  int sx[6], sy[6], sz[6];
+  stencil6(a.g, c, 0, sx);
+  stencil6(a.g, c, 1, sy);
+  stencil6(a.g, c, 2, sz);
+  const int* st[3] = {sx, sy, sz};
+  a.e[2][c.id] = uct_one<2>(a, c.id, st);
+  a.e[0][c.id] = uct_one<0>(a, c.id, st);
+  a.e[1][c.id] = uct_one<1>(a, c.id, st);
 }
-template void launch_uct<double>(int, const UctArgs<double>&, hipStream_t);
-template void launch_uct<float>(int, const UctArgs<float>&, hipStream_t);
+
+template <typename TS>
+void launch_uct3(const Uct3Args<TS>& a, hipStream_t s) {
+  hipLaunchKernelGGL((k_uct3<TS>), cell_grid(a.g), dim3(kBlockX, kBlockY), 0, s, a);
+}
+template void launch_uct3<double>(const Uct3Args<double>&, hipStream_t);
+template void launch_uct3<float>(const Uct3Args<float>&, hipStream_t);
 
 // -------------------------------------------------- DER + RK3 stage update
 // L(U) at centres: -sum_d (Fhat(+d face) - Fhat(-d face))/dx_d; at faces:
 // dB_d/dt = -(d_p E_q - d_q E_p), (d, p, q) cyclic.  SSP-RK3 (Shu & Osher):
-// stage 1: U1 = U0 + dt L; stage 2: 3/4 U0 + 1/4 (U1 + dt L);
-// stage 3: 1/3 U0 + 2/3 (U2 + dt L).  Stage 0 writes L only.
+// stage 1: U1 = U^n + dt L(U^n); stage 2: U2 = 3/4 U^n + 1/4 (U1 + dt L(U1));
+// stage 3: U^{n+1} = 1/3 U^n + 2/3 (U2 + dt L(U2)).  Stage 0 writes L only.
+// Stage 1 writes U1 to a work register, so U^n stays in the caller's arrays
+// and is read back by stages 2 and 3 (no copy of U^n).
 template <int STAGE, typename TS>
 __global__ __launch_bounds__(kThreads) void k_update(UpdArgs<TS> a) {
   const Cell c = cell_of(a.g);
@@ -596,21 +651,20 @@ __global__ __launch_bounds__(kThreads) void k_update(UpdArgs<TS> a) {
   const double dt = a.sc->dt;
 #pragma unroll
   for (int n = 0; n < 8; ++n) {
-    const double u = a.u[n][c.id];
+    const double u = a.ucur[n][c.id];
     if (STAGE == 1) {
-      a.u0[n][c.id] = u;
-      a.u[n][c.id] = u + dt * r[n];
+      a.uout[n][c.id] = u + dt * r[n];
     } else if (STAGE == 2) {
-      a.u[n][c.id] = 0.75 * a.u0[n][c.id] + 0.25 * (u + dt * r[n]);
+      a.uout[n][c.id] = 0.75 * a.u0[n][c.id] + 0.25 * (u + dt * r[n]);
     } else {
-      a.u[n][c.id] = (1.0 / 3.0) * a.u0[n][c.id] + (2.0 / 3.0) * (u + dt * r[n]);
+      a.uout[n][c.id] = (1.0 / 3.0) * a.u0[n][c.id] + (2.0 / 3.0) * (u + dt * r[n]);
     }
   }
 }
 
 template <typename TS>
 void launch_update(int stage, const UpdArgs<TS>& a, hipStream_t s) {
-  dim3 grid((a.g.nx + kBlockX - 1) / kBlockX, (a.g.ny + kBlockY - 1) / kBlockY, a.g.nz);
+  const dim3 grid = cell_grid(a.g);
   dim3 blk(kBlockX, kBlockY);
   switch (stage) {
     case 0: hipLaunchKernelGGL((k_update<0, TS>), grid, blk, 0, s, a); break;

@@ -91,17 +91,16 @@ struct FluxArgs {
   unsigned long long* counters;
 };
 
+// All three edge orientations in one pass (each face-B and speed array is
+// used by two orientations).
 template <typename TS>
-struct UctArgs {
+struct Uct3Args {
   GridDims g;
-  const TS* fvp[6];   // p-face velocity states (left xyz, right xyz)
-  const TS* app;      // a+ at p faces
-  const TS* amp;      // a- at p faces
-  const TS* apq;      // a+ at q faces
-  const TS* amq;      // a- at q faces
-  const double* bp;   // face B_p
-  const double* bq;   // face B_q
-  double* e;          // edge field E_k
+  const TS* fv[3][6];  // per face direction: left vx, vy, vz; right vx, vy, vz
+  const TS* ap[3];
+  const TS* am[3];
+  const double* bf[3];
+  double* e[3];
 };
 
 template <typename TS>
@@ -109,9 +108,10 @@ struct UpdArgs {
   GridDims g;
   const TS* fhat[3][5];
   const double* e[3];
-  double* u[8];       // state: D, Sx, Sy, Sz, U, Bx, By, Bz (in place)
-  double* u0[8];      // RK register U^n
-  double* rhs_out[8]; // stage 0: write L(U) here instead of updating
+  const double* ucur[8];  // the stage's input: D, Sx, Sy, Sz, U, Bx, By, Bz
+  const double* u0[8];    // U^n (stages 2 and 3)
+  double* uout[8];        // the stage's output (may alias ucur or u0 pointwise)
+  double* rhs_out[8];     // stage 0: write L(U) here instead of updating
   const DevScalars* sc;
 };
 
@@ -141,7 +141,7 @@ void launch_harvest(const HarvestArgs& a, hipStream_t s);
 template <typename TS>
 void launch_flux(int dir, const FluxArgs<TS>& a, bool cfl, bool stats, hipStream_t s);
 template <typename TS>
-void launch_uct(int k, const UctArgs<TS>& a, hipStream_t s);
+void launch_uct3(const Uct3Args<TS>& a, hipStream_t s);
 template <typename TS>
 void launch_update(int stage, const UpdArgs<TS>& a, hipStream_t s);
 void launch_dt(DevScalars* sc, double cfl, double dt_fixed, hipStream_t s);

@@ -40,15 +40,22 @@ __device__ __forceinline__ void face_eval(const FaceState<T>& s, T g, T g1,
                                           FaceEval<T>& e) {
   const T v2 = s.vn * s.vn + s.vt1 * s.vt1 + s.vt2 * s.vt2;
   const T one_m_v2 = T(1) - v2;
-  const T lor2 = T(1) / one_m_v2;
   const T rhoh = s.rho + g1 * s.p;
-  const T W = rhoh * lor2;
   // E = -v x B in the (n, t1, t2) frame
   const T En = s.vt2 * s.bt1 - s.vt1 * s.bt2;
   const T Et1 = s.vn * s.bt2 - s.vt2 * s.bn;
   const T Et2 = s.vt1 * s.bn - s.vn * s.bt1;
   const T E2 = En * En + Et1 * Et1 + Et2 * Et2;
   const T B2 = s.bn * s.bn + s.bt1 * s.bt1 + s.bt2 * s.bt2;
+  const T vB = s.vn * s.bn + s.vt1 * s.bt1 + s.vt2 * s.bt2;
+  const T b2 = B2 * one_m_v2 + vB * vB;  // comoving field strength squared
+  // one division for 1/(1 - v^2), 1/(rho h) and 1/(rho h + b^2)
+  const T q1 = rhoh * (rhoh + b2);
+  const T r = T(1) / (one_m_v2 * q1);
+  const T lor2 = q1 * r;                       // 1/(1 - v^2)
+  const T inv_rhoh = one_m_v2 * (rhoh + b2) * r;
+  const T inv_rhohb = one_m_v2 * rhoh * r;
+  const T W = rhoh * lor2;
   const T pm = T(0.5) * (E2 + B2);
   const T D = s.rho * sqrt(lor2);
   const T Sn = W * s.vn + (Et1 * s.bt2 - Et2 * s.bt1);
@@ -64,14 +71,12 @@ __device__ __forceinline__ void face_eval(const FaceState<T>& s, T g, T g1,
   e.f[3] = Wvn * s.vt2 - Et2 * En - s.bt2 * s.bn;
   e.f[4] = Sn;
   // fast-speed bound
-  const T inv_rhoh = T(1) / rhoh;
   const T cs2 = g * s.p * inv_rhoh;
-  const T vB = s.vn * s.bn + s.vt1 * s.bt1 + s.vt2 * s.bt2;
-  const T b2 = B2 * one_m_v2 + vB * vB;
-  const T va2 = b2 / (rhoh + b2);
+  const T va2 = b2 * inv_rhohb;
   const T w2 = cs2 + va2 - cs2 * va2;
-  const T inv_den = T(1) / (T(1) - v2 * w2);
-  T disc = w2 * one_m_v2 * ((T(1) - v2 * w2) - s.vn * s.vn * (T(1) - w2));
+  const T den = T(1) - v2 * w2;
+  const T inv_den = T(1) / den;
+  T disc = w2 * one_m_v2 * (den - s.vn * s.vn * (T(1) - w2));
   disc = disc > T(0) ? disc : T(0);
   const T sqd = sqrt(disc);
   const T a = s.vn * (T(1) - w2);
@@ -90,20 +95,23 @@ __device__ __forceinline__ bool face_state_ok(const FaceState<T>& s) {
 // x_{i+1/2} from v_{i-2..i+2}, alpha = 4, eps = 1e-10.  The right state at the
 // same face is the mirror call mp5(v_{i+3}, v_{i+2}, v_{i+1}, v_i, v_{i-1}).
 
+// minmod(a, b) = (sgn a + sgn b)/2 * min(|a|, |b|) and
+// minmod4(a, b, c, d) = (sgn a + sgn b)/8 * |(sgn a + sgn c)(sgn a + sgn d)| *
+// min(|a|, |b|, |c|, |d|): the common-sign minimum, else zero.  With sgn taken
+// as copysign(1, .) a zero argument makes the minimum zero, so both are exact
+// (the factors are 0 or +-1) and branch-free.
 template <typename T>
 __device__ __forceinline__ T minmod2(T a, T b) {
-  const bool same = (a > T(0) && b > T(0)) || (a < T(0) && b < T(0));
-  const T m = fabs(a) < fabs(b) ? a : b;
-  return same ? m : T(0);
+  const T s = T(0.5) * (copysign(T(1), a) + copysign(T(1), b));
+  return s * fmin(fabs(a), fabs(b));
 }
 
 template <typename T>
 __device__ __forceinline__ T minmod4(T a, T b, T c, T d) {
-  const bool pos = a > T(0) && b > T(0) && c > T(0) && d > T(0);
-  const bool neg = a < T(0) && b < T(0) && c < T(0) && d < T(0);
-  const T mn = fmin(fmin(a, b), fmin(c, d));
-  const T mx = fmax(fmax(a, b), fmax(c, d));
-  return pos ? mn : (neg ? mx : T(0));
+  const T sa = copysign(T(1), a);
+  const T s = T(0.125) * (sa + copysign(T(1), b)) *
+              fabs((sa + copysign(T(1), c)) * (sa + copysign(T(1), d)));
+  return s * fmin(fmin(fabs(a), fabs(b)), fmin(fabs(c), fabs(d)));
 }
 
 template <typename T>
@@ -128,6 +136,52 @@ __device__ __forceinline__ T mp5(T vm2, T vm1, T v0, T vp1, T vp2) {
   return vor + minmod2(vmin - vor, vmax - vor);
 }
 
+// Both states at the face x_{i+1/2} from s[0..5] = v_{i-2..i+3}: left =
+// mp5(s0..s4), right = mp5(s5..s1).  Same arithmetic as two mp5 calls, but
+// the curvatures d_i, d_{i+1} and d^{M4}_{i+1/2} (minmod4 is symmetric in its
+// pair) are computed once for both sides, and only when a side needs its
+// limiter.
+template <typename T>
+__device__ __forceinline__ void mp5_pair(T s0, T s1, T s2, T s3, T s4, T s5, T& left, T& right) {
+  const T c60 = T(1.0 / 60.0);
+  // left: centre s2; right: centre s3, mirrored
+  const T vorL = s2 + (T(2) * (s0 - s2) - T(13) * (s1 - s2) + T(27) * (s3 - s2) -
+                       T(3) * (s4 - s2)) * c60;
+  const T vorR = s3 + (T(2) * (s5 - s3) - T(13) * (s4 - s3) + T(27) * (s2 - s3) -
+                       T(3) * (s1 - s3)) * c60;
+  const T dlL = s2 - s1, dlR = s3 - s4;
+  const T vmpL = s2 + minmod2(s3 - s2, T(4) * dlL);
+  const T vmpR = s3 + minmod2(s2 - s3, T(4) * dlR);
+  const bool okL = (vorL - s2) * (vorL - vmpL) <= T(1e-10);
+  const bool okR = (vorR - s3) * (vorR - vmpR) <= T(1e-10);
+  left = vorL;
+  right = vorR;
+  if (okL && okR) return;
+  const T d1 = s0 - T(2) * s1 + s2;  // d_{i-1}
+  const T d2 = s1 - T(2) * s2 + s3;  // d_i
+  const T d3 = s2 - T(2) * s3 + s4;  // d_{i+1}
+  const T d4 = s3 - T(2) * s4 + s5;  // d_{i+2}
+  const T m23 = minmod4(T(4) * d2 - d3, T(4) * d3 - d2, d2, d3);  // d^{M4}_{i+1/2}
+  if (!okL) {
+    const T m12 = minmod4(T(4) * d2 - d1, T(4) * d1 - d2, d2, d1);  // d^{M4}_{i-1/2}
+    const T vul = s2 + T(4) * dlL;
+    const T vmd = T(0.5) * (s2 + s3) - T(0.5) * m23;
+    const T vlc = s2 + T(0.5) * dlL + T(4.0 / 3.0) * m12;
+    const T vmin = fmax(fmin(fmin(s2, s3), vmd), fmin(fmin(s2, vul), vlc));
+    const T vmax = fmin(fmax(fmax(s2, s3), vmd), fmax(fmax(s2, vul), vlc));
+    left = vorL + minmod2(vmin - vorL, vmax - vorL);
+  }
+  if (!okR) {
+    const T m34 = minmod4(T(4) * d3 - d4, T(4) * d4 - d3, d3, d4);  // d^{M4}_{i+3/2}
+    const T vul = s3 + T(4) * dlR;
+    const T vmd = T(0.5) * (s3 + s2) - T(0.5) * m23;
+    const T vlc = s3 + T(0.5) * dlR + T(4.0 / 3.0) * m34;
+    const T vmin = fmax(fmin(fmin(s3, s2), vmd), fmin(fmin(s3, vul), vlc));
+    const T vmax = fmin(fmax(fmax(s3, s2), vmd), fmax(fmax(s3, vul), vlc));
+    right = vorR + minmod2(vmin - vorR, vmax - vorR);
+  }
+}
+
 // ------------------------------------------------------------- UCT formula
 // Londrillo & Del Zanna (2004) upwind edge field for an edge along k with
 // (p, q, k) cyclic: four corner values E[ab] (a = side along p, b = side along
@@ -137,10 +191,16 @@ template <typename T>
 __device__ __forceinline__ T uct_edge(T ELL, T ELR, T ERL, T ERR, T app, T apm,
                                       T aqp, T aqm, T bqL, T bqR, T bpL, T bpR) {
   const T sp = app + apm, sq_ = aqp + aqm;
-  T e;
   if (sp > T(0) && sq_ > T(0)) {
-    e = (app * aqp * ELL + app * aqm * ELR + apm * aqp * ERL + apm * aqm * ERR) / (sp * sq_);
-  } else if (sp > T(0)) {
+    // one reciprocal for the weights and both dissipation coefficients
+    const T inv = T(1) / (sp * sq_);
+    const T e = (app * aqp * ELL + app * aqm * ELR + apm * aqp * ERL + apm * aqm * ERR) * inv;
+    const T dp = app * apm * sq_ * inv;
+    const T dq = aqp * aqm * sp * inv;
+    return e + dp * (bqR - bqL) - dq * (bpR - bpL);
+  }
+  T e;
+  if (sp > T(0)) {
     e = (app * (ELL + ELR) + apm * (ERL + ERR)) / (T(2) * sp);
   } else if (sq_ > T(0)) {
     e = (aqp * (ELL + ERL) + aqm * (ELR + ERR)) / (T(2) * sq_);

@@ -113,3 +113,43 @@ class Mlp:
         n = torch.tensor(self.norm, dtype=torch.float32, device=self.device)
         y = self.forward(self.standardise(feats))
         return y * n[12:14] + n[10:12]
+
+
+def harvest_training_set(device="cuda", turb_n=64, sigmas=(1.0, 3.0, 10.0), gamma_max=5.0,
+                         snapshots=4, steps_between=3, frac=0.05, seed=10):
+    """(features, targets) harvested by the solver itself: the CPA waves on
+    the axis and the diagonal at 32^3, and the turbulence set-up at turb_n^3
+    for each magnetisation in `sigmas`, at `snapshots` times a few steps
+    apart."""
+    from . import inputs
+    from .solver import Solver
+    feats, targs = [], []
+    for diag in (False, True):
+        prim5, bf, _ = inputs.cpa(32, diagonal=diag)
+        S = Solver(32, device=device)
+        S.init(prim5, bf)
+        S.step(2)
+        f, t = S.harvest(4096, 0.1, seed=1)
+        feats.append(f)
+        targs.append(t)
+        S.close()
+    cap = int(turb_n ** 3 * frac * 1.3) + 64
+    for sig in sigmas:
+        prim5, bf = inputs.turbulence(turb_n, sigma0=sig, gamma_max=gamma_max, device=device)
+        S = Solver(turb_n, pfloor=1e-10, device=device)
+        S.init(prim5, bf)
+        for k in range(snapshots):
+            f, t = S.harvest(cap, frac, seed=seed + k)
+            feats.append(f)
+            targs.append(t)
+            S.step(steps_between)
+        S.close()
+    return torch.cat(feats), torch.cat(targs)
+
+
+def train_default(device="cuda", steps=1500, seed=0):
+    """The network used by the learned form: trained on harvest_training_set()."""
+    feats, targs = harvest_training_set(device)
+    mlp = Mlp(seed=seed, device=device)
+    hist = mlp.fit(feats, targs, steps=steps, batch=4096, lr=2e-3, seed=1, log_every=250)
+    return mlp, hist, feats.shape[0]

@@ -1,0 +1,120 @@
+"""Long-run driver for the decaying-turbulence set-up: steps the solver in one
+form (FP64 or mixed, previous-step or learned Newton guess) and logs
+max|div_h B|, Newton statistics and shell-binned spectra of v and B.
+
+The spectra are diagnostics off the hot path (torch FFT on the primitives the
+library returns); every step of the solver runs in libsrmhd.
+"""
+from __future__ import annotations
+
+import math
+import time
+
+import torch
+
+from . import inputs
+from .solver import Solver
+
+
+def shell_spectrum(fields, nbins=None):
+    """E(k) = sum over |k| in [k - 1/2, k + 1/2) of |FFT(f)|^2 / N^2, summed
+    over the components in `fields` (list of (nz, ny, nx) tensors); k in units
+    of the box wave number."""
+    nz, ny, nx = fields[0].shape
+    kx = torch.fft.rfftfreq(nx, d=1.0 / nx, device=fields[0].device)
+    ky = torch.fft.fftfreq(ny, d=1.0 / ny, device=fields[0].device)
+    kz = torch.fft.fftfreq(nz, d=1.0 / nz, device=fields[0].device)
+    K = torch.sqrt(kz[:, None, None] ** 2 + ky[None, :, None] ** 2 + kx[None, None, :] ** 2)
+    nbins = nbins or int(min(nx, ny, nz) // 2)
+    shell = torch.round(K).long().clamp(max=nbins)
+    # rfft keeps half the x spectrum: weight the doubled modes
+    w = torch.full((nx // 2 + 1,), 2.0, device=K.device, dtype=torch.float64)
+    w[0] = 1.0
+    if nx % 2 == 0:
+        w[-1] = 1.0
+    N = float(nx * ny * nz)
+    E = torch.zeros(nbins + 1, dtype=torch.float64, device=K.device)
+    for f in fields:
+        F = torch.fft.rfftn(f - f.mean())
+        P = (F.real ** 2 + F.imag ** 2) * w[None, None, :] / (N * N)
+        E.index_add_(0, shell.reshape(-1), P.reshape(-1))
+        del F, P
+    return E[1:nbins].cpu()
+
+
+def turbulence_run(n, steps, precision="fp64", mlp=None, sigma0=10.0, gamma_max=5.0,
+                   log_every=10, spectrum_every=100, device="cuda", verbose=True):
+    """Run the turbulence set-up at n^3; returns a dict of logs."""
+    prim5, bf = inputs.turbulence(n, sigma0=sigma0, gamma_max=gamma_max, device=device)
+    S = Solver(n, precision=precision, pfloor=1e-10, collect_stats=True, device=device)
+    S.init(prim5, bf)
+    del prim5, bf
+    torch.cuda.empty_cache()
+    if mlp is not None:
+        S.set_mlp(mlp)
+        S.set_guess("mlp")
+    log = {"n": n, "precision": precision, "learned": mlp is not None, "divb": [], "spectra": [],
+           "newton": None}
+    t0 = time.perf_counter()
+    done = 0
+    while done < steps:
+        if done % spectrum_every == 0:
+            P = S.primitives()
+            ev = shell_spectrum([P[1], P[2], P[3]])
+            eb = shell_spectrum([P[5], P[6], P[7]])
+            t, _, _ = S.time()
+            log["spectra"].append({"step": done, "t": t, "E_v": ev.tolist(), "E_B": eb.tolist()})
+            del P
+        k = min(log_every, steps - done)
+        S.step(k)
+        done += k
+        d = S.diagnostics(raise_on_error=False)
+        log["divb"].append((done, d["t"], d["divb_max"] / n))
+        if verbose:
+            print(f"[run] {precision}{'+learned' if mlp else ''} {n}^3 step {done} t={d['t']:.4f} "
+                  f"divB*dx={d['divb_max'] / n:.2e} rc={d['rc']}", flush=True)
+        if d["rc"] != 0:
+            log["error"] = d["rc"]
+            break
+    torch.cuda.synchronize()
+    log["seconds"] = time.perf_counter() - t0
+    d = S.diagnostics(raise_on_error=False)
+    h = d["newton_hist"]
+    tot = max(sum(h), 1)
+    cdf, acc = [], 0
+    for c in h:
+        acc += c
+        cdf.append(acc / tot)
+    log["newton"] = {"mean": d["newton_iters"] / max(d["newton_calls"], 1),
+                     "p50": next(i for i, c in enumerate(cdf) if c >= 0.5),
+                     "p99": next(i for i, c in enumerate(cdf) if c >= 0.99),
+                     "mlp_fallback_rate": d["mlp_fallbacks"] / max(d["newton_calls"], 1),
+                     "floors": d["floors"], "c2p_failures": d["c2p_failures"],
+                     "recon_fallbacks": d["recon_fallbacks"]}
+    log["Mcell_updates_per_s"] = n ** 3 * done / log["seconds"] / 1e6
+    P = S.primitives()
+    log["final_prims"] = P
+    S.close()
+    return log
+
+
+def spectral_slope(E, kmin=3, kmax=None):
+    """Least-squares slope of log E against log k over [kmin, kmax]."""
+    kmax = kmax or len(E)
+    ks = torch.arange(1, len(E) + 1, dtype=torch.float64)
+    sel = (ks >= kmin) & (ks <= kmax) & (torch.as_tensor(E) > 0)
+    x = torch.log(ks[sel])
+    y = torch.log(torch.as_tensor(E, dtype=torch.float64)[sel])
+    A = torch.stack([x, torch.ones_like(x)], 1)
+    sol = torch.linalg.lstsq(A, y[:, None]).solution
+    return float(sol[0, 0])
+
+
+def compare_runs(a, b, scale=1.0):
+    """Per-variable L1 relative difference of two runs' final primitives."""
+    out = []
+    for q in range(8):
+        d = (a["final_prims"][q] - b["final_prims"][q]).abs().sum().item()
+        r = max(b["final_prims"][q].abs().sum().item(), b["final_prims"][q].numel() * scale)
+        out.append(d / r)
+    return out

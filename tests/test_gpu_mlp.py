@@ -132,26 +132,8 @@ def test_harvest_matches_oracle():
 def _train_on_runs(steps=1500):
     """Pairs harvested from the solver itself: the CPA waves (C1/C2 type) and
     64^3 turbulence at sigma0 = 1, 3, 10, a few steps into each run."""
-    from paper_2401_03008_amd.solver import Solver
-    feats, targs = [], []
-    for diag in (False, True):
-        prim5, bf, _ = I.cpa(32, diagonal=diag)
-        S = Solver(32)
-        S.init(prim5, bf)
-        S.step(2)
-        f, t = S.harvest(4096, 0.1, seed=1)
-        feats.append(f), targs.append(t)
-        S.close()
-    for sig in (1.0, 3.0, 10.0):
-        prim5, bf = I.turbulence(64, sigma0=sig, gamma_max=5.0)
-        S = Solver(64, pfloor=1e-10)
-        S.init(prim5, bf)
-        for k in range(4):
-            f, t = S.harvest(16384, 0.05, seed=10 + k)
-            feats.append(f), targs.append(t)
-            S.step(3)
-        S.close()
-    feats, targs = torch.cat(feats), torch.cat(targs)
+    from paper_2401_03008_amd.learned import harvest_training_set
+    feats, targs = harvest_training_set()
     mlp = _mlp(0)
     hist = mlp.fit(feats, targs, steps=steps, batch=4096, lr=2e-3, seed=1, log_every=250)
     return mlp, feats, targs, hist
@@ -241,3 +223,21 @@ def test_iteration_report_turbulence():
     a = (prims["mlp"] - prims["prev"]).abs().sum().item() / prims["prev"].abs().sum().item()
     assert a < 1e-10
     assert rows["cold"]["mean_iters"] > rows["prev"]["mean_iters"]
+
+
+def test_turbulence_run_driver_small():
+    """The long-run driver at 64^3: mixed + learned against plain FP64 over
+    20 steps -- same answer to the mixed form's precision, div B at round-off,
+    spectra logged."""
+    from paper_2401_03008_amd.learned import Mlp
+    from paper_2401_03008_amd.runs import compare_runs, turbulence_run
+    mlp, *_ = _train_on_runs(steps=300)
+    a = turbulence_run(64, 20, precision="fp64", log_every=10, spectrum_every=10)
+    b = turbulence_run(64, 20, precision="mixed", mlp=mlp, log_every=10, spectrum_every=10)
+    assert "error" not in a and "error" not in b
+    assert max(x[2] for x in a["divb"]) < 1e-11 and max(x[2] for x in b["divb"]) < 1e-11
+    assert len(a["spectra"]) == 2 and len(a["spectra"][0]["E_v"]) == 31
+    diff = compare_runs(b, a)
+    print("[gpu] mixed+learned vs fp64 (64^3 turbulence, 20 steps):", ["%.1e" % d for d in diff],
+          "newton", a["newton"], b["newton"], flush=True)
+    assert max(diff) < 1e-4
