@@ -30,37 +30,69 @@ FP32_PEAK_TFLOPS = 157.3    # MI355X FP32 vector (packed)
 STEP_BYTES = 560.0          # algorithmic HBM bytes per cell-step of the state
 
 # Algorithmic HBM bytes and FP64/FP32 arithmetic operations per unit (cell,
-# face or edge) of each kernel, for the plain FP64 form and the mixed form.
-# Bytes: every array element the kernel must read or write, once.  Flops:
-# adds, multiplies, divides and square roots of the formulas (FMA = 2), MP5
-# counted on its limiter path (49 per call, 14 calls per face, 12 per edge;
-# the UCT kernel computes the three edges of a cell).
+# face or edge) of each kernel class, for the plain FP64 form and the mixed
+# form, averaged over the class's launches in one step.  Bytes: every array
+# element the kernel must read or write, once.  flux: 7 primitives + normal B
+# in, 5 fluxes + a+- + 4 face velocities out (the z pass of stage 1 also reads
+# the x and y speeds for the CFL sum: (184 + 152 + 152)/3).  uct: 12 face
+# velocities + 6 speeds + 3 face B in, 3 edge fields out.  update: stage 1
+# reads 15 fluxes, 3 edge fields and U^n and writes the RK register; stages 2
+# and 3 also read U^n ((272 + 336 + 336)/3).  Flops: adds, multiplies,
+# divides and square roots of the formulas (FMA = 2), MP5 counted on its
+# limiter path (49 per call, 14 calls per face, 12 per edge; the UCT kernel
+# computes the three edges of a cell).
 KERNEL_UNITS = {
     # class: (bytes fp64, bytes mixed, flops per unit)
     "c2p": (144.0, 112.0, 200.0),
-    "flux_x": (168.0, 88.0, 940.0),
-    "flux_y": (168.0, 88.0, 940.0),
-    "flux_z": (168.0, 88.0, 940.0),
+    "flux_x": (152.0, 80.0, 940.0),
+    "flux_y": (152.0, 80.0, 940.0),
+    "flux_z": (488.0 / 3, 256.0 / 3, 940.0),
     "uct": (192.0, 120.0, 1920.0),
-    "update": (336.0, 276.0, 80.0),
+    "update": (944.0 / 3, 764.0 / 3, 80.0),
+}
+# rocprofv3 kernel names of each class's FP64 launches in one step (name,
+# launches per step), for the HBM traffic read from the profiles
+PROFILED_KERNEL = {
+    "c2p": [("k_c2p<false, false>", 3)],
+    "flux_x": [("k_flux<0, double, false, false>", 3)],
+    "flux_y": [("k_flux<1, double, false, false>", 3)],
+    "flux_z": [("k_flux<2, double, true, false>", 1), ("k_flux<2, double, false, false>", 2)],
+    "uct": [("k_uct3<double>", 3)],
+    "update": [("k_update<1, double>", 1), ("k_update<2, double>", 1), ("k_update<3, double>", 1)],
 }
 
 
-def profiled_traffic(kernel_name):
-    """HBM bytes per launch of `kernel_name` from the committed rocprofv3
-    summaries (FETCH_SIZE and WRITE_SIZE scaled by a plain copy's readings),
-    or None when the kernel source changed since the counters were taken."""
-    import glob
+KERNEL_SOURCES = ("srmhd_kernels.hip", "srmhd_kernels.hpp", "srmhd_phys.hpp")
+
+
+def kernel_sources_sha():
+    """sha256[:16] over the stage kernels' sources, in KERNEL_SOURCES order."""
     import hashlib
-    src = os.path.join(ROOT, "paper_2401_03008_amd", "csrc", "srmhd_kernels.hip")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2401_03008_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(kernel_cls):
+    """HBM bytes per launch of class `kernel_cls`, averaged over its launches
+    in one step, from the committed rocprofv3 summaries (FETCH_SIZE and
+    WRITE_SIZE scaled by a plain copy's readings), or None when the kernel
+    sources changed since the counters were taken."""
+    import glob
+    sha = kernel_sources_sha()
     for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.txt"))):
         txt = open(f).read()
-        if f"srmhd_kernels.hip: {sha}" not in txt:
+        if f"kernel sources sha256[:16]: {sha}" not in txt:
             continue
+        got = {}
         for line in txt.splitlines():
-            if line.startswith("traffic_bytes_per_launch ") and kernel_name in line:
-                return int(line.rsplit(":", 1)[1])
+            if line.startswith("traffic_bytes_per_launch "):
+                name, val = line[len("traffic_bytes_per_launch "):].rsplit(":", 1)
+                got[name.strip()] = int(val)
+        parts = PROFILED_KERNEL[kernel_cls]
+        if all(k in got for k, _ in parts):
+            return int(sum(got[k] * w for k, w in parts) / sum(w for _, w in parts))
     return None
 
 
@@ -109,25 +141,89 @@ def run_form(n, precision, steps, warmup, mlp=None):
 
 
 def cpu_baseline(seconds_target=15.0):
-    """The oracle (as it stands) on the same wave at 64^3, all host cores."""
+    """The oracle (as it stands) on the same wave at 64^3, on all host cores,
+    then on one thread."""
     import oracle
     from paper_2401_03008_amd import inputs
     oracle.build(force=False)
     n = 64
     prim5, bf, _ = inputs.cpa(n, diagonal=True)
     g = oracle.Grid(n)
-    cons, W = g.init(prim5, bf)
-    t0 = time.perf_counter()
-    g.step(cons, bf, W, 1)
-    one = time.perf_counter() - t0
-    nsteps = max(1, min(8, int(seconds_target / max(one, 1e-3))))
-    t0 = time.perf_counter()
-    g.step(cons, bf, W, nsteps)
-    el = time.perf_counter() - t0
-    return {"value": n ** 3 * nsteps / el / 1e6, "unit": "Mcell-updates/s",
-            "cores": oracle.num_threads(), "kind": "oracle",
+
+    def rate(max_steps):
+        cons, W = g.init(prim5, bf)
+        t0 = time.perf_counter()
+        g.step(cons, bf, W, 1)
+        one = time.perf_counter() - t0
+        nsteps = max(1, min(max_steps, int(seconds_target / max(one, 1e-3))))
+        t0 = time.perf_counter()
+        g.step(cons, bf, W, nsteps)
+        el = time.perf_counter() - t0
+        return n ** 3 * nsteps / el / 1e6, nsteps, el
+
+    cores = oracle.num_threads()
+    v, nsteps, el = rate(8)
+    oracle.set_num_threads(1)
+    v1, nsteps1, el1 = rate(3)
+    oracle.set_num_threads(cores)
+    return {"value": v, "unit": "Mcell-updates/s", "cores": cores, "kind": "oracle",
             "sample": f"diagonal CPA {n}^3, {nsteps} RK3 steps after 1 warm-up step, FP64, "
-                      f"OpenMP over z ({el:.1f} s)"}
+                      f"OpenMP over z ({el:.1f} s)",
+            "single_thread_value": v1,
+            "single_thread_sample": f"same wave, {nsteps1} steps on 1 thread ({el1:.1f} s)"}
+
+
+def newton_report_turbulence(n, mlp, steps=4):
+    """Newton iterations per inversion on the turbulence set-up at n^3
+    (sigma0 = 10, Gamma up to 5) with the previous-step W, the learned guess
+    and a cold start (W0 = U): each from the same state (2 steps in), over
+    the same `steps` steps; mean/p50/p99 iterations, fallback rate, k_c2p ms,
+    and the learned run's L1 difference from the previous-W run."""
+    import torch
+    from paper_2401_03008_amd import inputs
+    from paper_2401_03008_amd.solver import Solver
+    prim5, bf = inputs.turbulence(n, sigma0=10.0, gamma_max=5.0, device="cuda")
+    rows, ref = {}, None
+    for guess in ("prev", "mlp", "cold"):
+        S = Solver(n, pfloor=1e-10, collect_stats=True)
+        S.init(prim5, bf)
+        S.step(2)
+        if guess == "mlp":
+            S.set_mlp(mlp)
+        S.set_guess(guess)
+        S.reset_counters()
+        S.kernel_timing(True)
+        S.step(steps)
+        kt = S.kernel_times()
+        S.kernel_timing(False)
+        d = S.diagnostics(raise_on_error=False)
+        S.set_guess("prev")
+        h = d["newton_hist"]
+        tot = max(sum(h), 1)
+        cdf, acc = [], 0
+        for c in h:
+            acc += c
+            cdf.append(acc / tot)
+        row = {"mean_iters": round(d["newton_iters"] / max(d["newton_calls"], 1), 3),
+               "p50": next(i for i, c in enumerate(cdf) if c >= 0.5),
+               "p99": next(i for i, c in enumerate(cdf) if c >= 0.99),
+               "fallback_rate": round(d["mlp_fallbacks"] / max(d["newton_calls"], 1), 5),
+               "c2p_ms": round(kt["c2p"][0] / max(kt["c2p"][1], 1), 4),
+               "c2p_failures": d["c2p_failures"], "rc": d["rc"]}
+        P = S.primitives()
+        if guess == "prev":
+            ref = P
+        else:
+            row["l1_rel_vs_prev"] = float((P - ref).abs().sum() / ref.abs().sum())
+            del P
+        rows[guess] = row
+        S.close()
+        del S
+        torch.cuda.empty_cache()
+    del ref, prim5, bf
+    torch.cuda.empty_cache()
+    rows["workload"] = f"turbulence {n}^3, sigma0 = 10, Gamma <= 5, {steps} steps after 2"
+    return rows
 
 
 def main():
@@ -150,7 +246,7 @@ def main():
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the "
-              "multi-GPU decomposition is not part of this build.", file=sys.stderr)
+              "multi-GPU domain decomposition is not implemented.", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -221,9 +317,7 @@ def main():
             roof = {"bound": "alu", "achieved": round(tfl, 3), "peak": fpeak,
                     "unit": "TFLOP/s", "frac": round(tfl / fpeak, 4), "traffic": None}
         if args.precision == "fp64" and n == 256:
-            dom_name = {"update": "k_update<2, double>"}.get(dom)
-            tr = profiled_traffic(dom_name) if dom_name else None
-            roof["traffic"] = tr
+            roof["traffic"] = profiled_traffic(dom)
         roof.update({"kernel": dom, "avg_ms": round(kernels[dom]["avg_ms"], 4),
                      "alg_bytes_per_launch": bytes_per, "alg_flops_per_launch": flops_per,
                      "alu_tflops": round(tfl, 3), "hbm_gbs": round(gbs, 1)})
@@ -247,6 +341,8 @@ def main():
             forms[key] = run_form(args.forms_n, prec, max(5, args.steps // 2), 2, mlp=mlp)
         forms["learned_training"] = {"pairs": npairs, "adam_steps": 1500, "batch": 4096,
                                      "final_loss": hist[-1][1], "seconds": round(train_s, 2)}
+        print(f"[bench] Newton report, turbulence {args.forms_n}^3", file=sys.stderr, flush=True)
+        forms["newton_turbulence"] = newton_report_turbulence(args.forms_n, mlp)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -41,7 +41,8 @@ class _Cfg(C.Structure):
                 ("lx", C.c_double), ("ly", C.c_double), ("lz", C.c_double),
                 ("gam", C.c_double), ("cfl", C.c_double), ("dt_fixed", C.c_double),
                 ("riemann", C.c_int), ("maxit", C.c_int), ("tol", C.c_double),
-                ("pfloor", C.c_double)]
+                ("pfloor", C.c_double), ("recon", C.c_int), ("time_order", C.c_int),
+                ("ho", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -95,6 +96,10 @@ def lib():
         L.orc_divb_max.restype = _D
         L.orc_sums.argtypes = [cp, _PP, _PP, _PD]
         L.orc_num_threads.restype = C.c_int
+        for name in ("orc_mc", "orc_int_ho", "orc_der_ho"):
+            getattr(L, name).argtypes = [_PD]
+            getattr(L, name).restype = _D
+        L.orc_set_num_threads.argtypes = [C.c_int]
         _lib = L
     return _lib
 
@@ -106,6 +111,10 @@ def _vec(x, n):
 
 def num_threads() -> int:
     return lib().orc_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    lib().orc_set_num_threads(int(n))
 
 
 # ---------------------------------------------------------------- point ops
@@ -146,6 +155,25 @@ def mp5(s):
     return lib().orc_mp5(pa)
 
 
+def mc(s):
+    """Left-biased linear MC value at x_{i+1/2} from (v_{i-1}, v_i, v_{i+1})."""
+    a, pa = _vec(s, 3)
+    return lib().orc_mc(pa)
+
+
+def int_ho(b):
+    """Sixth-order centre value from the six face values b_{i-5/2..i+5/2}."""
+    a, pa = _vec(b, 6)
+    return lib().orc_int_ho(pa)
+
+
+def der_ho(f):
+    """Fhat(i+1/2) - Fhat(i-1/2) from point fluxes f_{i-5/2..i+5/2} (times
+    1/dx this is the sixth-order derivative at x_i)."""
+    a, pa = _vec(f, 6)
+    return lib().orc_der_ho(pa)
+
+
 def riemann(prL, prR, d, kind=0, gam=4.0 / 3.0):
     a, pa = _vec(prL, 8)
     b, pb = _vec(prR, 8)
@@ -178,12 +206,14 @@ class Grid:
 
     def __init__(self, nx, ny=None, nz=None, lx=1.0, ly=1.0, lz=1.0,
                  gam=4.0 / 3.0, cfl=0.5, dt_fixed=0.0, riemann=0, maxit=50,
-                 tol=1e-14, pfloor=0.0):
+                 tol=1e-14, pfloor=0.0, recon=0, time_order=3, ho=0):
+        """recon: 0 = MP5, 1 = linear MC; time_order: 3 (SSP-RK3) or 2
+        (SSP-RK2); ho: 1 = sixth-order INT and DER corrections."""
         ny = nx if ny is None else ny
         nz = nx if nz is None else nz
         self.shape = (nz, ny, nx)
         self.cfg = _Cfg(nx, ny, nz, lx, ly, lz, gam, cfl, dt_fixed, riemann,
-                        maxit, tol, pfloor)
+                        maxit, tol, pfloor, recon, time_order, ho)
         self.stats = Stats()
 
     def _z(self, n):

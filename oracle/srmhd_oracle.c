@@ -41,6 +41,25 @@
  *     the residual (8 ulps of the sum of its terms over the slope).
  *   - Time: SSP-RK3 of Shu & Osher (1988), dt = cfl / max_cells
  *     sum_d max(a+, a-)_d / dx_d from the first-stage speeds.
+ * Variants the paper names without formulas (Sec. 3 and the benchmark
+ * section): HO = YES (high-order INT and DER) and second-order time stepping
+ * with linear reconstruction.  Readings:
+ *   - HO INT: the sixth-order central interpolation of the six face values
+ *     around the centre, weights (3, -25, 150, 150, -25, 3)/256.
+ *   - HO DER: each point-value face flux f is replaced by
+ *     Fhat = f - D2 f / 24 + 3 D4 f / 640 (D2, D4 the second and fourth
+ *     undivided differences along the derivative direction), the sixth-order
+ *     form whose differences give the derivative at the centre; applied to
+ *     the fluid fluxes and to the edge fields of the curl.  The curl of
+ *     corrected edge fields conserves the divergence taken with the same
+ *     corrected differences of the face B, which is the div B diagnostic in
+ *     this mode.
+ *   - Linear reconstruction: slope = MC(v_i - v_{i-1}, v_{i+1} - v_i) with
+ *     the monotonized-central limiter of van Leer (1977),
+ *     MC(a, b) = sign(a) min(2|a|, 2|b|, |a + b|/2) if ab > 0, else 0;
+ *     face values v_i +- slope/2; used for the fluxes and for UCT.
+ *   - Second-order time: SSP-RK2, U1 = U0 + dt L(U0),
+ *     U = 1/2 U0 + 1/2 (U1 + dt L(U1)).
  */
 #include "srmhd_oracle.h"
 
@@ -255,9 +274,24 @@ static double minmod4(double a, double b, double c, double d) {
 /* Left-biased value at x_{i+1/2} from s = {v_{i-2}, v_{i-1}, v_i, v_{i+1},
  * v_{i+2}}.  The right-biased value at the same face is this function applied
  * to {v_{i+3}, v_{i+2}, v_{i+1}, v_i, v_{i-1}}. */
+static double mp5_limit(const double *s, double vor);
+
 double orc_mp5(const double *s) {
+  const double vor = (2.0 * s[0] - 13.0 * s[1] + 47.0 * s[2] + 27.0 * s[3] - 3.0 * s[4]) / 60.0;
+  return mp5_limit(s, vor);
+}
+
+/* The same limiter around the fifth-order interpolation of point values,
+ * weights (3, -20, 90, 60, -5)/128: the REC of the HO scheme, whose DER
+ * correction expects face point values. */
+double orc_mp5_point(const double *s) {
+  const double vor = (3.0 * s[0] - 20.0 * s[1] + 90.0 * s[2] + 60.0 * s[3] - 5.0 * s[4]) / 128.0;
+  return mp5_limit(s, vor);
+}
+
+/* MP limiter of Suresh & Huynh around the unlimited value vor. */
+static double mp5_limit(const double *s, double vor) {
   const double vm2 = s[0], vm1 = s[1], v0 = s[2], vp1 = s[3], vp2 = s[4];
-  const double vor = (2.0 * vm2 - 13.0 * vm1 + 47.0 * v0 + 27.0 * vp1 - 3.0 * vp2) / 60.0;
   const double vmp = v0 + minmod2(vp1 - v0, MP5_ALPHA * (v0 - vm1));
   if ((vor - v0) * (vor - vmp) <= MP5_EPS) return vor;
   const double djm1 = vm2 - 2.0 * vm1 + v0;
@@ -273,6 +307,38 @@ double orc_mp5(const double *s) {
   const double vmax = fmin(fmax(fmax(v0, vp1), vmd), fmax(fmax(v0, vul), vlc));
   return vor + minmod2(vmin - vor, vmax - vor);
 }
+
+/* ------------------------------------------------------------------------ */
+/* Linear REC with the MC limiter; high-order INT and DER                   */
+/* ------------------------------------------------------------------------ */
+
+/* Left-biased value at x_{i+1/2} from s = {v_{i-1}, v_i, v_{i+1}}; the
+ * right-biased value is this function of {v_{i+2}, v_{i+1}, v_i}. */
+double orc_mc(const double *s) {
+  const double a = s[1] - s[0], b = s[2] - s[1];
+  double slope = 0.0;
+  if (a * b > 0.0) {
+    const double m = fmin(fmin(2.0 * fabs(a), 2.0 * fabs(b)), 0.5 * fabs(a + b));
+    slope = a > 0.0 ? m : -m;
+  }
+  return s[1] + 0.5 * slope;
+}
+
+/* Centre value from the face values b = {B_{i-5/2}, ..., B_{i+5/2}}. */
+double orc_int_ho(const double *b) {
+  return (3.0 * b[0] - 25.0 * b[1] + 150.0 * b[2] + 150.0 * b[3] - 25.0 * b[4] + 3.0 * b[5]) /
+         256.0;
+}
+
+/* Corrected flux at the middle face of g = {f_{-2}, ..., f_{+2}}. */
+static double fhat_ho(const double *g) {
+  const double d2 = g[3] - 2.0 * g[2] + g[1];
+  const double d4 = g[4] - 4.0 * g[3] + 6.0 * g[2] - 4.0 * g[1] + g[0];
+  return g[2] - d2 / 24.0 + 3.0 * d4 / 640.0;
+}
+
+/* Fhat(i+1/2) - Fhat(i-1/2) from f = {f_{i-5/2}, ..., f_{i+5/2}}. */
+double orc_der_ho(const double *f) { return fhat_ho(f + 1) - fhat_ho(f); }
 
 /* ------------------------------------------------------------------------ */
 /* Upwind face flux (HLL / LLF)                                              */
@@ -351,21 +417,61 @@ static double cell_width(const orc_cfg *c, int d) {
   return d == 0 ? c->lx / c->nx : (d == 1 ? c->ly / c->ny : c->lz / c->nz);
 }
 
-/* INT (second order): centred B_d is the mean of the two d-faces. */
+/* INT: centred B_d is the mean of the two d-faces (second order), or the
+ * sixth-order interpolation of the six nearest d-faces (HO). */
 static double int_bc(const orc_cfg *c, double *const *bf, int i, int j, int k, int d) {
+  if (c->ho) {
+    double b[6];
+    for (int m = 0; m < 6; ++m) b[m] = bf[d][idx_shift(c, i, j, k, d, m - 3)];
+    return orc_int_ho(b);
+  }
   return 0.5 * (bf[d][idx_shift(c, i, j, k, d, -1)] + bf[d][idx_shift(c, i, j, k, d, 0)]);
 }
 
-/* MP5 left and right values at the +face along d of cell (i,j,k). */
+/* d/dx_d at the centre of cell (i,j,k) of a quantity a given at the +d
+ * faces (a[id] sits at +1/2 along d): plain difference, or the HO form. */
+static double der_at(const orc_cfg *c, const double *a, int i, int j, int k, int d, double dx) {
+  if (c->ho) {
+    double f[6];
+    for (int m = 0; m < 6; ++m) f[m] = a[idx_shift(c, i, j, k, d, m - 3)];
+    return orc_der_ho(f) / dx;
+  }
+  return (a[idx_shift(c, i, j, k, d, 0)] - a[idx_shift(c, i, j, k, d, -1)]) / dx;
+}
+
+/* Left and right values at the face between st[2] and st[3] of the six
+ * values st = {v_{i-2}, ..., v_{i+3}}: MP5 (kind 0), linear MC (1), or MP5
+ * around the point-value interpolation (2, the HO scheme). */
+static void rec_pair(int recon, const double *st, double *l, double *r) {
+  if (recon == 2) {
+    const double s[5] = {st[0], st[1], st[2], st[3], st[4]};
+    const double t[5] = {st[5], st[4], st[3], st[2], st[1]};
+    *l = orc_mp5_point(s);
+    *r = orc_mp5_point(t);
+    return;
+  }
+  if (recon == 1) {
+    const double s[3] = {st[1], st[2], st[3]};
+    const double t[3] = {st[4], st[3], st[2]};
+    *l = orc_mc(s);
+    *r = orc_mc(t);
+    return;
+  }
+  const double s[5] = {st[0], st[1], st[2], st[3], st[4]};
+  const double t[5] = {st[5], st[4], st[3], st[2], st[1]};
+  *l = orc_mp5(s);
+  *r = orc_mp5(t);
+}
+
+static int rec_kind(const orc_cfg *c) { return c->recon == 1 ? 1 : (c->ho ? 2 : 0); }
+
+/* Left and right values (MP5, or linear MC) at the +face along d of cell
+ * (i,j,k). */
 static void rec_face(const orc_cfg *c, const double *a, int i, int j, int k, int d,
                      double *vl, double *vr) {
-  double s[5], r[5];
-  for (int m = 0; m < 5; ++m) {
-    s[m] = a[idx_shift(c, i, j, k, d, m - 2)];
-    r[m] = a[idx_shift(c, i, j, k, d, 3 - m)];
-  }
-  *vl = orc_mp5(s);
-  *vr = orc_mp5(r);
+  double st[6];
+  for (int m = 0; m < 6; ++m) st[m] = a[idx_shift(c, i, j, k, d, m - 2)];
+  rec_pair(rec_kind(c), st, vl, vr);
 }
 
 static int state_ok(const double *pr) {
@@ -423,24 +529,18 @@ typedef struct {
   double app[2], amp[2], aqp[2], aqm[2];
 } edge_in;
 
-static void rec5(const double *st, double *l, double *r) {
-  const double s[5] = {st[0], st[1], st[2], st[3], st[4]};
-  const double t[5] = {st[5], st[4], st[3], st[2], st[1]};
-  *l = orc_mp5(s);
-  *r = orc_mp5(t);
-}
 
-/* UCT edge field: corner states by MP5 along q of the p-face states, B_p
+/* UCT edge field: corner states by REC along q of the p-face states, B_p
  * along q, B_q along p, E^{ab} = v_q^{ab} B_p^b - v_p^{ab} B_q^a, edge speeds
  * the maxima over the two adjacent faces of each direction. */
-static double edge_from(const edge_in *e) {
+static double edge_from(int recon, const edge_in *e) {
   double vp[2][2], vq[2][2], bpL, bpR, bqL, bqR;
   for (int a = 0; a < 2; ++a) {
-    rec5(e->vp[a], &vp[a][0], &vp[a][1]);
-    rec5(e->vq[a], &vq[a][0], &vq[a][1]);
+    rec_pair(recon, e->vp[a], &vp[a][0], &vp[a][1]);
+    rec_pair(recon, e->vq[a], &vq[a][0], &vq[a][1]);
   }
-  rec5(e->bp, &bpL, &bpR);
-  rec5(e->bq, &bqL, &bqR);
+  rec_pair(recon, e->bp, &bpL, &bpR);
+  rec_pair(recon, e->bq, &bqL, &bqR);
   double Eab[4];
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b) {
@@ -595,7 +695,7 @@ int orc_rhs(const orc_cfg *c, double *const *prim, double *const *bf, double **r
           e.aqp[1] = apm[2 * q][idp];
           e.aqm[0] = apm[2 * q + 1][id];
           e.aqm[1] = apm[2 * q + 1][idp];
-          ee[kk][id] = edge_from(&e);
+          ee[kk][id] = edge_from(rec_kind(c), &e);
         }
   }
 
@@ -607,17 +707,15 @@ int orc_rhs(const orc_cfg *c, double *const *prim, double *const *bf, double **r
         const long id = ((long)k * c->ny + j) * c->nx + i;
         for (int n = 0; n < 5; ++n) {
           double s = 0.0;
-          for (int d = 0; d < 3; ++d) {
-            const long im = idx_shift(c, i, j, k, d, -1);
-            s += (fh[5 * d + n][id] - fh[5 * d + n][im]) / dxs[d];
-          }
+          for (int d = 0; d < 3; ++d) s += der_at(c, fh[5 * d + n], i, j, k, d, dxs[d]);
           rhs[n][id] = -s;
         }
-        /* dB_d/dt = -(curl E)_d, (curl E)_d = d_p E_q - d_q E_p, (d,p,q) cyclic */
+        /* dB_d/dt = -(curl E)_d, (curl E)_d = d_p E_q - d_q E_p, (d,p,q) cyclic;
+         * E_q sits at +1/2 along p and E_p at +1/2 along q */
         for (int d = 0; d < 3; ++d) {
           const int p = (d + 1) % 3, q = (d + 2) % 3;
-          const double dpEq = (ee[q][id] - ee[q][idx_shift(c, i, j, k, p, -1)]) / dxs[p];
-          const double dqEp = (ee[p][id] - ee[p][idx_shift(c, i, j, k, q, -1)]) / dxs[q];
+          const double dpEq = der_at(c, ee[q], i, j, k, p, dxs[p]);
+          const double dqEp = der_at(c, ee[p], i, j, k, q, dxs[q]);
           rhs[5 + d][id] = -(dpEq - dqEp);
         }
       }
@@ -684,7 +782,7 @@ static double edge_at(const orc_cfg *c, double *const *prim, double *const *bf, 
     e.aqp[m] = fo.ap;
     e.aqm[m] = fo.am;
   }
-  return edge_from(&e);
+  return edge_from(rec_kind(c), &e);
 }
 
 /* L(U) at the listed cells only (linear indices cells[0..ncells-1]), with the
@@ -693,31 +791,41 @@ static double edge_at(const orc_cfg *c, double *const *prim, double *const *bf, 
 int orc_rhs_cells(const orc_cfg *c, double *const *prim, double *const *bf, int ncells,
                   const long *cells, double *out) {
   const double dxs[3] = {cell_width(c, 0), cell_width(c, 1), cell_width(c, 2)};
+  /* faces (or edges) at offsets m0 .. m0+nm-1 along the derivative direction */
+  const int m0 = c->ho ? -3 : -1, nm = c->ho ? 6 : 2;
 #pragma omp parallel for schedule(dynamic)
   for (int sidx = 0; sidx < ncells; ++sidx) {
     const long id = cells[sidx];
     const int q0[3] = {(int)(id % c->nx), (int)((id / c->nx) % c->ny),
                        (int)(id / ((long)c->nx * c->ny))};
-    face_out fp[3], fm[3];
-    for (int d = 0; d < 3; ++d) {
-      face_solve(c, prim, bf, q0[0], q0[1], q0[2], d, &fp[d]);
-      int m3[3] = {q0[0], q0[1], q0[2]};
-      shift_cell(c, m3, d, -1);
-      face_solve(c, prim, bf, m3[0], m3[1], m3[2], d, &fm[d]);
-    }
+    double fl[3][5][6];
+    for (int d = 0; d < 3; ++d)
+      for (int m = 0; m < nm; ++m) {
+        int a3[3] = {q0[0], q0[1], q0[2]};
+        shift_cell(c, a3, d, m0 + m);
+        face_out fo;
+        face_solve(c, prim, bf, a3[0], a3[1], a3[2], d, &fo);
+        for (int n = 0; n < 5; ++n) fl[d][n][m] = fo.fhat[n];
+      }
     for (int n = 0; n < 5; ++n) {
       double s = 0.0;
-      for (int d = 0; d < 3; ++d) s += (fp[d].fhat[n] - fm[d].fhat[n]) / dxs[d];
+      for (int d = 0; d < 3; ++d)
+        s += c->ho ? orc_der_ho(fl[d][n]) / dxs[d] : (fl[d][n][1] - fl[d][n][0]) / dxs[d];
       out[8L * sidx + n] = -s;
     }
     for (int d = 0; d < 3; ++d) {
       const int p = (d + 1) % 3, q = (d + 2) % 3;
-      int a3[3] = {q0[0], q0[1], q0[2]};
-      int b3[3] = {q0[0], q0[1], q0[2]};
-      shift_cell(c, a3, p, -1);
-      shift_cell(c, b3, q, -1);
-      const double dpEq = (edge_at(c, prim, bf, q0, q) - edge_at(c, prim, bf, a3, q)) / dxs[p];
-      const double dqEp = (edge_at(c, prim, bf, q0, p) - edge_at(c, prim, bf, b3, p)) / dxs[q];
+      double eq[6], ep[6];
+      for (int m = 0; m < nm; ++m) {
+        int a3[3] = {q0[0], q0[1], q0[2]};
+        int b3[3] = {q0[0], q0[1], q0[2]};
+        shift_cell(c, a3, p, m0 + m);
+        shift_cell(c, b3, q, m0 + m);
+        eq[m] = edge_at(c, prim, bf, a3, q);
+        ep[m] = edge_at(c, prim, bf, b3, p);
+      }
+      const double dpEq = c->ho ? orc_der_ho(eq) / dxs[p] : (eq[1] - eq[0]) / dxs[p];
+      const double dqEp = c->ho ? orc_der_ho(ep) / dxs[q] : (ep[1] - ep[0]) / dxs[q];
       out[8L * sidx + 5 + d] = -(dpEq - dqEp);
     }
   }
@@ -727,6 +835,8 @@ int orc_rhs_cells(const orc_cfg *c, double *const *prim, double *const *bf, int 
 /* nsteps full SSP-RK3 steps (Shu & Osher 1988):
  *   U1 = U0 + dt L(U0);  U2 = 3/4 U0 + 1/4 (U1 + dt L(U1));
  *   U  = 1/3 U0 + 2/3 (U2 + dt L(U2)),
+ * or, with time_order 2, SSP-RK2 steps:
+ *   U1 = U0 + dt L(U0);  U  = 1/2 U0 + 1/2 (U1 + dt L(U1)),
  * applied to the 5 cell-centred arrays and the 3 face-B arrays.  dt comes from
  * the first stage of each step (or cfg dt_fixed).  W is the Newton guess,
  * updated by every inversion.  Returns the number of failed inversions. */
@@ -744,7 +854,8 @@ int orc_step(const orc_cfg *c, double **cons, double **bf, double *W, int nsteps
   double dt = 0.0;
   for (int step = 0; step < nsteps; ++step) {
     for (int n = 0; n < 8; ++n) memcpy(u0[n], cur[n], sizeof(double) * N);
-    for (int s = 1; s <= 3; ++s) {
+    const int nstage = c->time_order == 2 ? 2 : 3;
+    for (int s = 1; s <= nstage; ++s) {
       nfail += orc_c2p(c, cons, bf, W, pr, NULL, st);
       double amax = 0.0;
       orc_rhs(c, pr, bf, rh, &amax, NULL, NULL, NULL, NULL, st);
@@ -756,6 +867,8 @@ int orc_step(const orc_cfg *c, double **cons, double **bf, double *W, int nsteps
         for (long id = 0; id < N; ++id) {
           if (s == 1)
             a[id] = a0[id] + dt * r[id];
+          else if (nstage == 2)
+            a[id] = 0.5 * a0[id] + 0.5 * (a[id] + dt * r[id]);
           else if (s == 2)
             a[id] = 0.75 * a0[id] + 0.25 * (a[id] + dt * r[id]);
           else
@@ -774,16 +887,16 @@ int orc_step(const orc_cfg *c, double **cons, double **bf, double *W, int nsteps
   return nfail;
 }
 
-/* max over cells of |div_h B| = |sum_d (B_d(+face) - B_d(-face)) / dx_d|. */
+/* max over cells of |div_h B| = |sum_d (B_d(+face) - B_d(-face)) / dx_d|,
+ * or with HO the same sum of corrected differences (the divergence that the
+ * HO curl keeps constant). */
 double orc_divb_max(const orc_cfg *c, double *const *bf) {
   double m = 0.0;
   for (int k = 0; k < c->nz; ++k)
     for (int j = 0; j < c->ny; ++j)
       for (int i = 0; i < c->nx; ++i) {
-        const long id = ((long)k * c->ny + j) * c->nx + i;
         double s = 0.0;
-        for (int d = 0; d < 3; ++d)
-          s += (bf[d][id] - bf[d][idx_shift(c, i, j, k, d, -1)]) / cell_width(c, d);
+        for (int d = 0; d < 3; ++d) s += der_at(c, bf[d], i, j, k, d, cell_width(c, d));
         if (fabs(s) > m) m = fabs(s);
       }
   return m;
@@ -806,5 +919,14 @@ int orc_num_threads(void) {
   return omp_get_max_threads();
 #else
   return 1;
+#endif
+}
+
+/* Set that number (n >= 1); no effect without OpenMP. */
+void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+  if (n >= 1) omp_set_num_threads(n);
+#else
+  (void)n;
 #endif
 }

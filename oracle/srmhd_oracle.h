@@ -42,6 +42,9 @@ typedef struct {
   int maxit;       /* Newton iteration cap */
   double tol;      /* Newton relative step tolerance on W */
   double pfloor;   /* pressure floor as a fraction of rho (0 = none) */
+  int recon;       /* 0 = MP5, 1 = linear with the MC limiter */
+  int time_order;  /* 3 = SSP-RK3, 2 = SSP-RK2 */
+  int ho;          /* 1 = high-order INT and DER (sixth-order central forms) */
 } orc_cfg;
 
 typedef struct {
@@ -59,6 +62,10 @@ void orc_speeds(double gam, const double *pr, int d, double *lm, double *lp);
 int orc_con2prim(double gam, const double *u, double *W, int maxit, double tol,
                  double pfloor, double *pr, int *iters, int *floored);
 double orc_mp5(const double *s);
+double orc_mp5_point(const double *s);
+double orc_mc(const double *s);
+double orc_int_ho(const double *b);
+double orc_der_ho(const double *f);
 void orc_riemann(int kind, double gam, const double *prL, const double *prR,
                  int d, double *fhat, double *ap, double *am);
 double orc_uct_formula(const double *Eab, double axp, double axm, double ayp,
@@ -79,6 +86,7 @@ int orc_step(const orc_cfg *c, double **cons, double **bf, double *W,
              int nsteps, double *t, double *dt_last, orc_stats *st);
 double orc_divb_max(const orc_cfg *c, double *const *bf);
 int orc_num_threads(void);
+void orc_set_num_threads(int n);
 void orc_sums(const orc_cfg *c, double *const *cons, double *const *bf,
               double *sums);
 

@@ -32,7 +32,7 @@ struct srmhd_ctx {
   float* prim32[8];
   void* fhat[3][5];
   void* apm[3][2];
-  void* fv[3][6];
+  void* fv[3][4];
   double* edge[3];
   std::string err;
   // per-kernel event timing
@@ -141,8 +141,8 @@ Layout layout_of(const srmhd_config* c) {
   const bool mixed = c->precision == SRMHD_MIXED;
   // RK register (8) + edge E (3) always FP64; prims FP64 (8) or FP32 (8); faces
   // (15 fluxes + 6 speeds + 18 velocity states) in the flux precision.
-  L.n64 = 8 + 3 + (mixed ? 0 : 8 + 39);
-  L.n32 = mixed ? 8 + 39 : 0;
+  L.n64 = 8 + 3 + (mixed ? 0 : 8 + 33);
+  L.n32 = mixed ? 8 + 33 : 0;
   L.total = L.off_arr + L.n64 * L.arr_bytes64 + L.n32 * L.arr_bytes32;
   return L;
 }
@@ -174,7 +174,7 @@ void stage_flux(srmhd_ctx* c, const StageState& st, bool cfl) {
     for (int n = 0; n < 5; ++n) a.fhat[n] = (TS*)c->fhat[d][n];
     a.ap = (TS*)c->apm[d][0];
     a.am = (TS*)c->apm[d][1];
-    for (int n = 0; n < 6; ++n) a.fv[n] = (TS*)c->fv[d][n];
+    for (int n = 0; n < 4; ++n) a.fv[n] = (TS*)c->fv[d][n];
     const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
     a.apm_other[0] = (const TS*)c->apm[t1][0];
     a.apm_other[1] = (const TS*)c->apm[t1][1];
@@ -195,7 +195,7 @@ void stage_uct_update(srmhd_ctx* c, const StageState& st, int stage, double* con
     Uct3Args<TS> a;
     a.g = c->g;
     for (int d = 0; d < 3; ++d) {
-      for (int n = 0; n < 6; ++n) a.fv[d][n] = (const TS*)c->fv[d][n];
+      for (int n = 0; n < 4; ++n) a.fv[d][n] = (const TS*)c->fv[d][n];
       a.ap[d] = (const TS*)c->apm[d][0];
       a.am[d] = (const TS*)c->apm[d][1];
       a.bf[d] = st.bf[d];
@@ -366,7 +366,7 @@ int srmhd_create(const srmhd_config* cfg, const srmhd_buffers* buf, void* stream
   for (int d = 0; d < 3; ++d) {
     for (int n = 0; n < 5; ++n) c->fhat[d][n] = takeT();
     for (int n = 0; n < 2; ++n) c->apm[d][n] = takeT();
-    for (int n = 0; n < 6; ++n) c->fv[d][n] = takeT();
+    for (int n = 0; n < 4; ++n) c->fv[d][n] = takeT();
   }
   // clear scalars and counters (a fill kernel, no memset node)
   launch_zero_u64((unsigned long long*)w, L.off_part / sizeof(unsigned long long), c->stream);

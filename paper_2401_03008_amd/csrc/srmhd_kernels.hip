@@ -23,50 +23,55 @@ struct Cell {
   bool valid;
 };
 
-// Tiles of 64 x 4 cells, launched as a 1D grid in x-fastest order.  (A remap
-// giving each of the 8 XCDs a contiguous slab of tiles -- workgroups go to the
-// XCDs round-robin -- measured 3-10% slower on the stencil kernels: eight
-// distant slabs then compete for the shared last-level cache, while the
-// natural order keeps all in-flight tiles within a few planes.)  Tiles past
-// the end of the padded grid have valid = false for the whole workgroup.
-constexpr int kXcds = 8;
-
-struct TileGrid {
-  int nbx, nby, ntiles;
+// Tiles of 64 x BY x BZ cells (BY * BZ <= 16 wavefronts), launched as a 1D
+// grid in x-fastest order.  A kernel with a stencil along y or z uses a tile
+// that is tall in that direction, so a workgroup fetches its rows or planes
+// plus a 5-cell halo into its XCD's L2 once instead of one halo per 4 rows.
+// (Remapping the 1D index so that each XCD owns a contiguous slab measured
+// 3-10% slower: eight distant slabs then compete for the shared last-level
+// cache.)  Lanes past the end of the box have valid = false.
+template <int BY, int BZ>
+struct Tile {
+  static constexpr int kY = BY, kZ = BZ, kThreads = kBlockX * BY * BZ;
 };
 
-__device__ __forceinline__ TileGrid tiles_of(const GridDims& g) {
-  TileGrid t;
-  t.nbx = (g.nx + kBlockX - 1) / kBlockX;
-  t.nby = (g.ny + kBlockY - 1) / kBlockY;
-  t.ntiles = t.nbx * t.nby * g.nz;
-  return t;
-}
-
-__device__ __forceinline__ int tile_index() { return blockIdx.x; }
-
-__device__ __forceinline__ Cell cell_of(const GridDims& g) {
-  const TileGrid t = tiles_of(g);
-  const int L = tile_index();
+template <int BY, int BZ>
+__device__ __forceinline__ Cell cell_of_tile(const GridDims& g) {
+  const int nbx = (g.nx + kBlockX - 1) / kBlockX, nby = (g.ny + BY - 1) / BY;
+  const int nbz = (g.nz + BZ - 1) / BZ;
+  const int L = blockIdx.x;
+  const int bx = L % nbx, r = L / nbx;
+  const int by = r % nby, bz = r / nby;
   Cell c;
-  const int bx = L % t.nbx, r = L / t.nbx;
-  const int by = r % t.nby, bz = r / t.nby;
   c.i = bx * kBlockX + threadIdx.x;
-  c.j = by * kBlockY + threadIdx.y;
-  c.k = bz;
-  c.valid = L < t.ntiles && c.i < g.nx && c.j < g.ny;
+  c.j = by * BY + threadIdx.y;
+  c.k = bz * BZ + threadIdx.z;
+  c.valid = bz < nbz && c.i < g.nx && c.j < g.ny && c.k < g.nz;
   c.id = c.valid ? (c.k * g.ny + c.j) * g.nx + c.i : 0;
   return c;
 }
 
+__device__ __forceinline__ Cell cell_of(const GridDims& g) { return cell_of_tile<kBlockY, 1>(g); }
+
 __device__ __forceinline__ int block_linear() { return blockIdx.x; }
 
-// 1D launch grid covering every tile, padded to a multiple of the XCD count.
-inline dim3 cell_grid(const GridDims& g) {
-  const long long n = (long long)((g.nx + kBlockX - 1) / kBlockX) *
-                      ((g.ny + kBlockY - 1) / kBlockY) * g.nz;
-  return dim3((unsigned)((n + kXcds - 1) / kXcds * kXcds));
+// wavefront index within the workgroup and number of wavefronts
+__device__ __forceinline__ int wave_in_block() { return threadIdx.z * blockDim.y + threadIdx.y; }
+__device__ __forceinline__ int waves_in_block() { return blockDim.y * blockDim.z; }
+
+template <int BY, int BZ>
+inline dim3 tile_grid(const GridDims& g) {
+  const long long n = (long long)((g.nx + kBlockX - 1) / kBlockX) * ((g.ny + BY - 1) / BY) *
+                      ((g.nz + BZ - 1) / BZ);
+  return dim3((unsigned)n);
 }
+
+template <int BY, int BZ>
+inline dim3 tile_block() {
+  return dim3(kBlockX, BY, BZ);
+}
+
+inline dim3 cell_grid(const GridDims& g) { return tile_grid<kBlockY, 1>(g); }
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x; }
 
@@ -116,7 +121,7 @@ struct BlockCounters {
   unsigned* s;
   __device__ void init(unsigned* sm) {
     s = sm;
-    const int tid = threadIdx.y * kBlockX + threadIdx.x;
+    const int tid = wave_in_block() * kBlockX + threadIdx.x;
     if (tid < CNT_N) s[tid] = 0;
     __syncthreads();
   }
@@ -138,7 +143,7 @@ struct BlockCounters {
   }
   __device__ void flush(unsigned long long* global) {
     __syncthreads();
-    const int tid = threadIdx.y * kBlockX + threadIdx.x;
+    const int tid = wave_in_block() * kBlockX + threadIdx.x;
     if (tid < CNT_N && s[tid])
       atomicAdd(&global[(block_linear() % kReplicas) * CNT_N + tid], (unsigned long long)s[tid]);
   }
@@ -428,18 +433,26 @@ void launch_harvest(const HarvestArgs& a, hipStream_t s) {
 // state with rho <= 0, p <= 0 or v^2 >= 1 is replaced by its cell's values
 // (first order) and counted.  HLL: a+ = max(0, l+_L, l+_R), a- = max(0, -l-_L,
 // -l-_R), Fhat = (a+ F_L + a- F_R - a+ a- (U_R - U_L))/(a+ + a-); LLF: a+ =
-// a- = max |l|.  Outputs the 5 fluid fluxes, a+-, and both velocity states
-// (for UCT).  With CFL, also the workgroup max of sum_d max(a+,a-)_d/dx_d
+// a- = max |l|.  Outputs the 5 fluid fluxes, a+-, and the left and right
+// states of v_DIR and v_{DIR+1}, the two velocity components that the edge
+// field E_{DIR+2} needs at these faces.  With CFL, also the workgroup max of sum_d max(a+,a-)_d/dx_d
 // (needs the other two directions' speeds already stored).
+// Tile per direction: 64x4x1 for x and y, 64x1x4 for z (the four wavefronts
+// of a z tile share 9 of their 24 stencil planes).  Measured at 256^3: the z
+// tile takes 3% off the z pass; taller tiles (64x16x1 for y, 64x1x16 for z)
+// were 10-14% slower.
+template <int DIR>
+struct FluxTile : Tile<DIR == 2 ? 1 : 4, DIR == 2 ? 4 : 1> {};
+
 template <int DIR, typename TS, bool CFL, bool STATS>
-__global__ __launch_bounds__(kThreads) void k_flux(FluxArgs<TS> a) {
+__global__ __launch_bounds__(FluxTile<DIR>::kThreads) void k_flux(FluxArgs<TS> a) {
   using T = TS;
   constexpr int T1 = (DIR + 1) % 3, T2 = (DIR + 2) % 3;
   __shared__ unsigned s_cnt[CNT_N];
-  __shared__ double s_max[kBlockY];
+  __shared__ double s_max[16];
   BlockCounters bc;
   if (STATS) bc.init(s_cnt);
-  const Cell c = cell_of(a.g);
+  const Cell c = cell_of_tile<FluxTile<DIR>::kY, FluxTile<DIR>::kZ>(a.g);
   int nfb = 0;
   double cfl_sum = 0.0;
   if (c.valid) {
@@ -499,12 +512,10 @@ __global__ __launch_bounds__(kThreads) void k_flux(FluxArgs<TS> a) {
     a.fhat[4][c.id] = F[4];
     a.ap[c.id] = ap;
     a.am[c.id] = am;
-    a.fv[DIR][c.id] = L.vn;
-    a.fv[T1][c.id] = L.vt1;
-    a.fv[T2][c.id] = L.vt2;
-    a.fv[3 + DIR][c.id] = R.vn;
-    a.fv[3 + T1][c.id] = R.vt1;
-    a.fv[3 + T2][c.id] = R.vt2;
+    a.fv[0][c.id] = L.vn;
+    a.fv[1][c.id] = L.vt1;
+    a.fv[2][c.id] = R.vn;
+    a.fv[3][c.id] = R.vt1;
     if (CFL) {
       // sum over d = 0, 1, 2 in that order; the other directions' speeds are
       // apm_other = {a+_T1, a-_T1, a+_T2, a-_T2}
@@ -517,11 +528,11 @@ __global__ __launch_bounds__(kThreads) void k_flux(FluxArgs<TS> a) {
   }
   if (CFL) {
     const double w = wave_max_f64(cfl_sum);
-    if (lane_id() == 0) s_max[threadIdx.y] = w;
+    if (lane_id() == 0) s_max[wave_in_block()] = w;
     __syncthreads();
-    if (threadIdx.x == 0 && threadIdx.y == 0) {
+    if (threadIdx.x == 0 && wave_in_block() == 0) {
       double b = s_max[0];
-      for (int n = 1; n < kBlockY; ++n) b = fmax(b, s_max[n]);
+      for (int n = 1; n < waves_in_block(); ++n) b = fmax(b, s_max[n]);
       // +double bit patterns order like unsigned integers; NaN sorts above inf
       atomicMax(a.amax_bits, (unsigned long long)__double_as_longlong(b));
     }
@@ -534,9 +545,10 @@ __global__ __launch_bounds__(kThreads) void k_flux(FluxArgs<TS> a) {
 
 template <typename TS>
 void launch_flux(int dir, const FluxArgs<TS>& a, bool cfl, bool stats, hipStream_t s) {
-  const dim3 grid = cell_grid(a.g);
-  dim3 blk(kBlockX, kBlockY);
-#define SRMHD_FLUX(D, C, S) hipLaunchKernelGGL((k_flux<D, TS, C, S>), grid, blk, 0, s, a)
+#define SRMHD_FLUX(D, C, S)                                                               \
+  hipLaunchKernelGGL((k_flux<D, TS, C, S>),                                               \
+                     (tile_grid<FluxTile<D>::kY, FluxTile<D>::kZ>(a.g)),                  \
+                     (tile_block<FluxTile<D>::kY, FluxTile<D>::kZ>()), 0, s, a)
   if (dir == 0) {
     if (stats) SRMHD_FLUX(0, false, true); else SRMHD_FLUX(0, false, false);
   } else if (dir == 1) {
@@ -572,8 +584,8 @@ __device__ __forceinline__ double uct_one(const Uct3Args<TS>& a, int id, const i
   double vp[2][2], vq[2][2];
 #pragma unroll
   for (int sd = 0; sd < 2; ++sd) {
-    rec(a.fv[P][3 * sd + P], iq, vp[sd][0], vp[sd][1]);
-    rec(a.fv[P][3 * sd + Q], iq, vq[sd][0], vq[sd][1]);
+    rec(a.fv[P][2 * sd], iq, vp[sd][0], vp[sd][1]);      // v_P
+    rec(a.fv[P][2 * sd + 1], iq, vq[sd][0], vq[sd][1]);  // v_Q, Q = P + 1 cyclically
   }
   double bpL, bpR, bqL, bqR;
   rec(a.bf[P], iq, bpL, bpR);
@@ -592,9 +604,13 @@ __device__ __forceinline__ double uct_one(const Uct3Args<TS>& a, int id, const i
                           bpL, bpR);
 }
 
+// The edge stencils run along all three directions; 64x4x1 tiles measured as
+// fast as 64x2x2 and faster than 64x4x4.
+using UctTile = Tile<4, 1>;
+
 template <typename TS>
-__global__ __launch_bounds__(kThreads) void k_uct3(Uct3Args<TS> a) {
-  const Cell c = cell_of(a.g);
+__global__ __launch_bounds__(UctTile::kThreads) void k_uct3(Uct3Args<TS> a) {
+  const Cell c = cell_of_tile<UctTile::kY, UctTile::kZ>(a.g);
   if (!c.valid) return;
   int sx[6], sy[6], sz[6];
   stencil6(a.g, c, 0, sx);
@@ -608,7 +624,8 @@ __global__ __launch_bounds__(kThreads) void k_uct3(Uct3Args<TS> a) {
 
 template <typename TS>
 void launch_uct3(const Uct3Args<TS>& a, hipStream_t s) {
-  hipLaunchKernelGGL((k_uct3<TS>), cell_grid(a.g), dim3(kBlockX, kBlockY), 0, s, a);
+  hipLaunchKernelGGL((k_uct3<TS>), (tile_grid<UctTile::kY, UctTile::kZ>(a.g)),
+                     (tile_block<UctTile::kY, UctTile::kZ>()), 0, s, a);
 }
 template void launch_uct3<double>(const Uct3Args<double>&, hipStream_t);
 template void launch_uct3<float>(const Uct3Args<float>&, hipStream_t);

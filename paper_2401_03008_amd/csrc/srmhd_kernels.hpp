@@ -83,7 +83,8 @@ struct FluxArgs {
   TS* fhat[5];         // D, Sx, Sy, Sz, U fluxes at the +face
   TS* ap;
   TS* am;
-  TS* fv[6];           // left vx, vy, vz; right vx, vy, vz at the +face
+  TS* fv[4];           // left v_n, v_t1; right v_n, v_t1 at the +face (t1 = next
+                       // direction cyclically: the components the edge fields use)
   const TS* apm_other[4];  // a+/a- of the other two directions (CFL fusion)
   unsigned long long* amax_bits;
   double gam;
@@ -96,7 +97,7 @@ struct FluxArgs {
 template <typename TS>
 struct Uct3Args {
   GridDims g;
-  const TS* fv[3][6];  // per face direction: left vx, vy, vz; right vx, vy, vz
+  const TS* fv[3][4];  // per face direction d: left v_d, v_{d+1}; right v_d, v_{d+1}
   const TS* ap[3];
   const TS* am[3];
   const double* bf[3];

@@ -46,6 +46,7 @@ def turbulence_run(n, steps, precision="fp64", mlp=None, sigma0=10.0, gamma_max=
                    log_every=10, spectrum_every=100, device="cuda", verbose=True):
     """Run the turbulence set-up at n^3; returns a dict of logs."""
     prim5, bf = inputs.turbulence(n, sigma0=sigma0, gamma_max=gamma_max, device=device)
+    torch.cuda.empty_cache()  # the generator's temporaries, before the solver's large blocks
     S = Solver(n, precision=precision, pfloor=1e-10, collect_stats=True, device=device)
     S.init(prim5, bf)
     del prim5, bf
@@ -118,3 +119,57 @@ def compare_runs(a, b, scale=1.0):
         r = max(b["final_prims"][q].abs().sum().item(), b["final_prims"][q].numel() * scale)
         out.append(d / r)
     return out
+
+
+def _summary(log):
+    """JSON-ready digest of a turbulence_run log (no tensors)."""
+    out = {k: log[k] for k in ("n", "precision", "learned", "seconds", "Mcell_updates_per_s",
+                               "newton") if k in log}
+    if "error" in log:
+        out["error"] = log["error"]
+    out["divb_max_dx"] = max(x[2] for x in log["divb"]) if log["divb"] else None
+    out["divb"] = log["divb"]
+    out["t_final"] = log["divb"][-1][1] if log["divb"] else 0.0
+    out["spectra"] = log["spectra"]
+    out["slopes_v_B"] = [(s["step"], spectral_slope(s["E_v"]), spectral_slope(s["E_B"]))
+                         for s in log["spectra"]]
+    return out
+
+
+def main(argv=None):
+    """Long run of the turbulence set-up: plain FP64 first, then the mixed
+    form with the learned guess from the same initial state, and the
+    per-variable L1 difference of their final primitives."""
+    import argparse
+    import json
+    ap = argparse.ArgumentParser(description=main.__doc__)
+    ap.add_argument("--n", type=int, default=768)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--log-every", type=int, default=10)
+    ap.add_argument("--spectrum-every", type=int, default=100)
+    ap.add_argument("--out", default=None, help="write the JSON summary here")
+    args = ap.parse_args(argv)
+    from .learned import train_default
+    mlp, hist, npairs = train_default()
+    print(f"[run] learned guess trained on {npairs} pairs, loss {hist[-1][1]:.2e}", flush=True)
+    res = {"workload": f"turbulence {args.n}^3, sigma0 = 10, Gamma <= 5, {args.steps} steps"}
+    a = turbulence_run(args.n, args.steps, "fp64", None, log_every=args.log_every,
+                       spectrum_every=args.spectrum_every)
+    a["final_prims"] = a["final_prims"].cpu()
+    torch.cuda.empty_cache()
+    b = turbulence_run(args.n, args.steps, "mixed", mlp, log_every=args.log_every,
+                       spectrum_every=args.spectrum_every)
+    b["final_prims"] = b["final_prims"].cpu()
+    res["fp64"] = _summary(a)
+    res["mixed+learned"] = _summary(b)
+    res["l1_rel_mixed_learned_vs_fp64"] = compare_runs(b, a)
+    print("[run] L1 rel (rho, vx, vy, vz, p, Bx, By, Bz):",
+          ["%.2e" % d for d in res["l1_rel_mixed_learned_vs_fp64"]], flush=True)
+    if args.out:
+        with open(args.out, "w") as f:
+            json.dump(res, f)
+    return res
+
+
+if __name__ == "__main__":
+    main()

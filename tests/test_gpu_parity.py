@@ -114,7 +114,8 @@ def test_inversion_cold_start_histogram():
 
 
 # ----------------------------------------------------------- spatial operator
-@pytest.mark.parametrize("shape,seed", [((12, 20, 72), 3), ((8, 8, 8), 4), ((9, 10, 11), 5)])
+@pytest.mark.parametrize("shape,seed", [((12, 20, 72), 3), ((8, 8, 8), 4), ((9, 10, 11), 5),
+                                        ((21, 18, 66), 6)])
 def test_rhs_matches_oracle_elementwise(shape, seed):
     """L(U) element by element on rough random states (ragged tiles, every
     MP5 branch, first-order fallbacks); amax exactly."""
