@@ -96,7 +96,7 @@ def lib():
         L.orc_divb_max.restype = _D
         L.orc_sums.argtypes = [cp, _PP, _PP, _PD]
         L.orc_num_threads.restype = C.c_int
-        for name in ("orc_mc", "orc_int_ho", "orc_der_ho"):
+        for name in ("orc_mc", "orc_int_ho", "orc_der_ho", "orc_mp5_point"):
             getattr(L, name).argtypes = [_PD]
             getattr(L, name).restype = _D
         L.orc_set_num_threads.argtypes = [C.c_int]
@@ -153,6 +153,13 @@ def con2prim(u, W, gam=4.0 / 3.0, maxit=50, tol=1e-14, pfloor=0.0):
 def mp5(s):
     a, pa = _vec(s, 5)
     return lib().orc_mp5(pa)
+
+
+def mp5_point(s):
+    """MP5 limiter around the 5-point interpolation of point values (the
+    HO scheme's REC)."""
+    a, pa = _vec(s, 5)
+    return lib().orc_mp5_point(pa)
 
 
 def mc(s):
