@@ -27,7 +27,11 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0       # MI355X HBM3E, GB/s
 FP64_PEAK_TFLOPS = 78.6     # MI355X FP64 vector
 FP32_PEAK_TFLOPS = 157.3    # MI355X FP32 vector (packed)
-STEP_BYTES = 560.0          # algorithmic HBM bytes per cell-step of the state
+# Algorithmic HBM bytes per cell-step of the state (FP64): each stage reads
+# the state (and U^n after the first stage) and W and writes the state and W:
+# SSP-RK3 144 + 208 + 208, SSP-RK2 144 + 208.
+STEP_BYTES = 560.0
+STEP_BYTES_RK2 = 352.0
 
 # Algorithmic HBM bytes and FP64/FP32 arithmetic operations per unit (cell,
 # face or edge) of each kernel class, for the plain FP64 form and the mixed
@@ -96,14 +100,15 @@ def profiled_traffic(kernel_cls):
     return None
 
 
-def run_form(n, precision, steps, warmup, mlp=None):
+def run_form(n, precision, steps, warmup, mlp=None, **scheme):
     """Mcell-updates/s of one form on the diagonal CPA at n^3 (mlp: the
-    learned Newton guess), then Newton statistics over 2 more steps."""
+    learned Newton guess; scheme: recon / time_order / high_order), then
+    Newton statistics over 2 more steps."""
     import torch
     from paper_2401_03008_amd import inputs
     from paper_2401_03008_amd.solver import Solver
     prim5, bf, _ = inputs.cpa(n, diagonal=True, device="cuda")
-    S = Solver(n, precision=precision, collect_stats=False)
+    S = Solver(n, precision=precision, collect_stats=False, **scheme)
     S.init(prim5, bf)
     del prim5, bf
     if mlp is not None:
@@ -121,7 +126,7 @@ def run_form(n, precision, steps, warmup, mlp=None):
     S.close()
     # Newton statistics of the same form (a separate run with counters on)
     prim5, bf, _ = inputs.cpa(n, diagonal=True, device="cuda")
-    S2 = Solver(n, precision=precision, collect_stats=True)
+    S2 = Solver(n, precision=precision, collect_stats=True, **scheme)
     S2.init(prim5, bf)
     del prim5, bf
     if mlp is not None:
@@ -133,9 +138,10 @@ def run_form(n, precision, steps, warmup, mlp=None):
     del S, S2
     torch.cuda.empty_cache()
     v = n ** 3 * steps / (ms / 1e3) / 1e6
+    sb = STEP_BYTES_RK2 if scheme.get("time_order", 3) == 2 else STEP_BYTES
     return {"cells": n ** 3, "steps": steps, "ms_per_step": round(ms / steps, 3),
             "Mcell_updates_per_s": round(v, 1),
-            "hbm_roofline_frac_step": round(v * 1e6 * STEP_BYTES / (HBM_PEAK_GBS * 1e9), 4),
+            "hbm_roofline_frac_step": round(v * 1e6 * sb / (HBM_PEAK_GBS * 1e9), 4),
             "newton_mean_iters": round(d["newton_iters"] / max(d["newton_calls"], 1), 3),
             "mlp_fallback_rate": round(d["mlp_fallbacks"] / max(d["newton_calls"], 1), 5)}
 
@@ -331,6 +337,14 @@ def main():
         for prec in ("fp64", "mixed"):
             print(f"[bench] form {prec} at {args.forms_n}^3", file=sys.stderr, flush=True)
             forms[prec] = run_form(args.forms_n, prec, max(5, args.steps // 2), 2)
+        # the paper's two other configurations: HO = YES (with UCT), and
+        # second-order time stepping with linear reconstruction
+        for prec in ("fp64", "mixed"):
+            for key, scheme in (("ho", dict(high_order=True)),
+                                ("mc+rk2", dict(recon="mc", time_order=2))):
+                name = f"{prec}+{key}"
+                print(f"[bench] form {name} at {args.forms_n}^3", file=sys.stderr, flush=True)
+                forms[name] = run_form(args.forms_n, prec, max(5, args.steps // 2), 2, **scheme)
         print("[bench] training the learned guess", file=sys.stderr, flush=True)
         t0 = time.perf_counter()
         mlp, hist, npairs = train_default()

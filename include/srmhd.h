@@ -47,6 +47,10 @@ extern "C" {
 enum { SRMHD_HLL = 0, SRMHD_LLF = 1 };
 enum { SRMHD_FP64 = 0, SRMHD_MIXED = 1 };
 enum { SRMHD_GUESS_PREV = 0, SRMHD_GUESS_MLP = 1, SRMHD_GUESS_COLD = 2 };
+/* Reconstruction (REC, Sec. 3): MP5 (Suresh & Huynh 1997), or linear with the
+ * monotonized-central limiter of van Leer (1977), the second-order option of
+ * the benchmark section. */
+enum { SRMHD_REC_MP5 = 0, SRMHD_REC_MC = 1 };
 
 /* Device error word bits (srmhd_diag.error_word). */
 #define SRMHD_ERRBIT_C2P 1u       /* an inversion did not converge */
@@ -68,6 +72,18 @@ typedef struct {
   double newton_tol;/* relative step tolerance on W (1e-14) */
   double pfloor;    /* pressure floor as a fraction of rho; 0 = none */
   int collect_stats;/* 1: Newton histogram / counters per inversion */
+  int recon;        /* SRMHD_REC_MP5 (default) or SRMHD_REC_MC */
+  int time_order;   /* 3: SSP-RK3 (default); 2: SSP-RK2 (Shu & Osher 1988),
+                       U1 = U0 + dt L(U0), U = (U0 + U1 + dt L(U1))/2 */
+  int high_order;   /* HO = YES of Sec. 3 (needs SRMHD_REC_MP5): sixth-order
+                       INT (3, -25, 150, 150, -25, 3)/256 of the six nearest
+                       faces; sixth-order DER of the face fluxes and of the
+                       edge fields in the curl, d/dx f = (-9 f_{-5/2} + 125
+                       f_{-3/2} - 2250 f_{-1/2} + 2250 f_{1/2} - 125 f_{3/2}
+                       + 9 f_{5/2}) / (1920 dx); MP5 around the point-value
+                       interpolation (3, -20, 90, 60, -5)/128.  div B in the
+                       diagnostics is then the same sixth-order difference
+                       of the face B, which the HO curl keeps constant. */
 } srmhd_config;
 
 typedef struct {
@@ -81,9 +97,10 @@ typedef struct {
 typedef struct {
   double t;              /* simulated time */
   double dt;             /* last timestep */
-  long step;             /* full RK3 steps taken */
+  long step;             /* full RK steps taken */
   double amax;           /* last max_cells sum_d max(a+,a-)_d/dx_d */
-  double divb_max;       /* max over cells |div_h B| */
+  double divb_max;       /* max over cells |div_h B| (sixth-order differences
+                            with high_order) */
   double sums[8];        /* sum over cells of D, Sx, Sy, Sz, U, Bx, By, Bz(face) */
   long newton_iters;     /* Newton iterations summed over inversions */
   long newton_calls;     /* inversions counted */
@@ -98,7 +115,8 @@ typedef struct {
 typedef struct srmhd_ctx srmhd_ctx;
 
 /* Fill *cfg with the defaults: 32^3 unit box, gamma 4/3, cfl 0.5, HLL, FP64,
- * previous-W guess, maxit 50, tol 1e-14, no floor, stats on. */
+ * previous-W guess, maxit 50, tol 1e-14, no floor, stats on, MP5, SSP-RK3,
+ * HO off. */
 int srmhd_config_default(srmhd_config *cfg);
 
 /* Size in bytes of the scratch a context with *cfg needs.  Validates *cfg;
@@ -113,18 +131,20 @@ int srmhd_create(const srmhd_config *cfg, const srmhd_buffers *buf,
 
 /* Set the state from cell-centred rho, vx, vy, vz, p (prim5, device) and
  * face B (bface, device; copied into the state's face arrays).  Conserved
- * variables follow Sec. 2 with centred B = INT (face average) of bface; the
+ * variables follow Sec. 2 with centred B = INT of bface (face average, or
+ * the sixth-order interpolation with high_order); the
  * guess W is set to rho h Gamma^2.  Resets t, step, counters and the error
  * word. */
 int srmhd_init_from_prims(srmhd_ctx *ctx, const double *const prim5[5],
                           const double *const bface[3]);
 
-/* Enqueue nsteps full SSP-RK3 steps (Shu & Osher 1988) of the Sec. 3 scheme:
- * per stage INT + Newton inversion, MP5 REC (Suresh & Huynh 1997) of rho, v,
- * p and transverse centred B, HLL/LLF face fluxes with the Del Zanna et al.
- * (2003) fast-speed bound, UCT edge fields (Londrillo & Del Zanna 2004),
- * flux divergence and curl; dt from the first stage's speeds.  Asynchronous;
- * t and dt stay on the device. */
+/* Enqueue nsteps full SSP-RK3 (or, with time_order 2, SSP-RK2) steps (Shu &
+ * Osher 1988) of the Sec. 3 scheme: per stage INT + Newton inversion, REC
+ * (MP5 of Suresh & Huynh 1997, or linear MC) of rho, v, p and transverse
+ * centred B, HLL/LLF face fluxes with the Del Zanna et al. (2003) fast-speed
+ * bound, UCT edge fields (Londrillo & Del Zanna 2004), flux divergence and
+ * curl (DER, sixth order with high_order); dt from the first stage's speeds.
+ * Asynchronous; t and dt stay on the device. */
 int srmhd_step(srmhd_ctx *ctx, int nsteps);
 
 /* Spatial operator on the current state: INT + inversion, then

@@ -25,6 +25,7 @@ SRMHD_E_STATE = -5
 SRMHD_HLL, SRMHD_LLF = 0, 1
 SRMHD_FP64, SRMHD_MIXED = 0, 1
 SRMHD_GUESS_PREV, SRMHD_GUESS_MLP, SRMHD_GUESS_COLD = 0, 1, 2
+SRMHD_REC_MP5, SRMHD_REC_MC = 0, 1
 ERRBIT_C2P, ERRBIT_NONFINITE, ERRBIT_DT, ERRBIT_PRESSURE = 1, 2, 4, 8
 
 
@@ -40,7 +41,8 @@ class Config(C.Structure):
                 ("gamma_ad", C.c_double), ("cfl", C.c_double), ("dt_fixed", C.c_double),
                 ("riemann", C.c_int), ("precision", C.c_int), ("guess", C.c_int),
                 ("newton_maxit", C.c_int), ("newton_tol", C.c_double),
-                ("pfloor", C.c_double), ("collect_stats", C.c_int)]
+                ("pfloor", C.c_double), ("collect_stats", C.c_int),
+                ("recon", C.c_int), ("time_order", C.c_int), ("high_order", C.c_int)]
 
 
 class Buffers(C.Structure):

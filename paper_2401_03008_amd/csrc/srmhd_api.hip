@@ -116,6 +116,10 @@ std::string validate(const srmhd_config* c) {
   if (c->newton_maxit < 1 || c->newton_maxit > 1000) return "newton_maxit must be in 1..1000";
   if (!(c->newton_tol > 0.0 && c->newton_tol < 1e-3)) return "newton_tol must be in (0, 1e-3)";
   if (!(c->pfloor >= 0.0 && c->pfloor < 1.0)) return "pfloor must be in [0, 1)";
+  if (c->recon != SRMHD_REC_MP5 && c->recon != SRMHD_REC_MC) return "recon must be MP5 or MC";
+  if (c->time_order != 2 && c->time_order != 3) return "time_order must be 2 or 3";
+  if (c->high_order != 0 && c->high_order != 1) return "high_order must be 0 or 1";
+  if (c->high_order && c->recon != SRMHD_REC_MP5) return "high_order needs MP5 reconstruction";
   return "";
 }
 
@@ -140,7 +144,7 @@ Layout layout_of(const srmhd_config* c) {
   L.arr_bytes32 = align_up(n * sizeof(float));
   const bool mixed = c->precision == SRMHD_MIXED;
   // RK register (8) + edge E (3) always FP64; prims FP64 (8) or FP32 (8); faces
-  // (15 fluxes + 6 speeds + 18 velocity states) in the flux precision.
+  // (15 fluxes + 6 speeds + 12 velocity states) in the flux precision.
   L.n64 = 8 + 3 + (mixed ? 0 : 8 + 33);
   L.n32 = mixed ? 8 + 33 : 0;
   L.total = L.off_arr + L.n64 * L.arr_bytes64 + L.n32 * L.arr_bytes32;
@@ -156,10 +160,16 @@ struct StageState {
 
 StageState stage_state(srmhd_ctx* c, int stage) {
   StageState s;
-  const bool reg = stage == 2 || stage == 3;
+  const bool reg = stage >= 2;
   for (int n = 0; n < 5; ++n) s.cons[n] = reg ? c->ureg[n] : c->buf.cons[n];
   for (int d = 0; d < 3; ++d) s.bf[d] = reg ? c->ureg[5 + d] : c->buf.bface[d];
   return s;
+}
+
+// REC kernel of the configuration: MC, or MP5 (point-value form with HO).
+int rec_kind(const srmhd_ctx* c) {
+  if (c->cfg.recon == SRMHD_REC_MC) return kRecMc;
+  return c->cfg.high_order ? kRecMp5Point : kRecMp5;
 }
 
 template <typename TS>
@@ -185,7 +195,7 @@ void stage_flux(srmhd_ctx* c, const StageState& st, bool cfl) {
     a.riemann = c->cfg.riemann;
     a.counters = c->counters;
     KTimer kt(c, 1 + d);
-    launch_flux<TS>(d, a, cfl && d == 2, stats, c->stream);
+    launch_flux<TS>(d, a, cfl && d == 2, stats, rec_kind(c), c->stream);
   }
 }
 
@@ -202,7 +212,7 @@ void stage_uct_update(srmhd_ctx* c, const StageState& st, int stage, double* con
       a.e[d] = c->edge[d];
     }
     KTimer kt(c, 4);
-    launch_uct3<TS>(a, c->stream);
+    launch_uct3<TS>(a, rec_kind(c), c->stream);
   }
   UpdArgs<TS> u;
   u.g = c->g;
@@ -215,12 +225,12 @@ void stage_uct_update(srmhd_ctx* c, const StageState& st, int stage, double* con
   for (int n = 0; n < 8; ++n) {
     u.ucur[n] = n < 5 ? st.cons[n] : st.bf[n - 5];
     u.u0[n] = state[n];
-    u.uout[n] = stage == 3 ? state[n] : c->ureg[n];
+    u.uout[n] = stage >= 3 ? state[n] : c->ureg[n];  // the last stage writes U^{n+1}
     u.rhs_out[n] = rhs_out ? rhs_out[n] : nullptr;
   }
   u.sc = c->sc;
   KTimer kt(c, 7);
-  launch_update<TS>(stage, u, c->stream);
+  launch_update<TS>(stage, u, c->cfg.high_order != 0, c->stream);
 }
 
 void launch_c2p_into(srmhd_ctx* c, const StageState& st, double* const* prim64,
@@ -239,6 +249,7 @@ void launch_c2p_into(srmhd_ctx* c, const StageState& st, double* const* prim64,
   a.pfloor = c->cfg.pfloor;
   a.maxit = c->cfg.newton_maxit;
   a.guess = guess;
+  a.ho = c->cfg.high_order;
   a.mlp = c->mlp;
   a.counters = c->counters;
   a.err = &c->sc->err;
@@ -246,7 +257,8 @@ void launch_c2p_into(srmhd_ctx* c, const StageState& st, double* const* prim64,
   launch_c2p(a, c->cfg.collect_stats != 0, c->stream);
 }
 
-// One RK stage (1..3), or stage 0 = L(U) into rhs_out.
+// One RK stage (1..3 of SSP-RK3; 1 and 4 of SSP-RK2), or stage 0 = L(U)
+// into rhs_out.
 int guess_code(const srmhd_ctx* c) {
   return c->cfg.guess == SRMHD_GUESS_COLD ? 2 : (c->cfg.guess == SRMHD_GUESS_MLP ? 1 : 0);
 }
@@ -295,6 +307,9 @@ int srmhd_config_default(srmhd_config* cfg) {
   cfg->newton_tol = 1e-14;
   cfg->pfloor = 0.0;
   cfg->collect_stats = 1;
+  cfg->recon = SRMHD_REC_MP5;
+  cfg->time_order = 3;
+  cfg->high_order = 0;
   return SRMHD_OK;
 }
 
@@ -389,6 +404,7 @@ int srmhd_init_from_prims(srmhd_ctx* c, const double* const prim5[5], const doub
     if (!bface[d]) return fail(c, SRMHD_E_INVAL, "bface entry is NULL");
   InitArgs a;
   a.g = c->g;
+  a.ho = c->cfg.high_order;
   for (int n = 0; n < 5; ++n) {
     a.prim5[n] = prim5[n];
     a.cons[n] = c->buf.cons[n];
@@ -417,8 +433,12 @@ int srmhd_step(srmhd_ctx* c, int nsteps) {
     return fail(c, SRMHD_E_STATE, "learned guess selected but no network set");
   for (int s = 0; s < nsteps; ++s) {
     run_stage(c, 1, nullptr);
-    run_stage(c, 2, nullptr);
-    run_stage(c, 3, nullptr);
+    if (c->cfg.time_order == 2) {
+      run_stage(c, 4, nullptr);
+    } else {
+      run_stage(c, 2, nullptr);
+      run_stage(c, 3, nullptr);
+    }
   }
   return check_launch(c, "step");
 }
@@ -457,6 +477,7 @@ int srmhd_get_diagnostics(srmhd_ctx* c, srmhd_diag* out) {
   if (c->initialized) {
     ReduceArgs a;
     a.g = c->g;
+    a.ho = c->cfg.high_order;
     for (int n = 0; n < 5; ++n) a.a[n] = c->buf.cons[n];
     for (int d = 0; d < 3; ++d) {
       a.a[5 + d] = c->buf.bface[d];
@@ -574,6 +595,7 @@ int srmhd_harvest(srmhd_ctx* c, float* feats, float* targets, int cap, double fr
     return fail(c, SRMHD_E_INVAL, "bad harvest arguments");
   HarvestArgs a;
   a.g = c->g;
+  a.ho = c->cfg.high_order;
   for (int n = 0; n < 5; ++n) a.cons[n] = c->buf.cons[n];
   for (int d = 0; d < 3; ++d) a.bf[d] = c->buf.bface[d];
   a.W = c->buf.guess_w;

@@ -75,19 +75,42 @@ inline dim3 cell_grid(const GridDims& g) { return tile_grid<kBlockY, 1>(g); }
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x; }
 
-// Stencil indices along direction dir at offsets -2..+3 (periodic).
-__device__ __forceinline__ void stencil6(const GridDims& g, const Cell& c, int dir, int* idx) {
+// Stencil indices along direction dir at offsets first..first+5 (periodic;
+// first >= -3 and the grid has >= 8 cells per direction).
+__device__ __forceinline__ void stencil6_from(const GridDims& g, const Cell& c, int dir,
+                                              int first, int* idx) {
   const int n = dir == 0 ? g.nx : (dir == 1 ? g.ny : g.nz);
   const int co = dir == 0 ? c.i : (dir == 1 ? c.j : c.k);
   const int stride = dir == 0 ? 1 : (dir == 1 ? g.nx : g.nx * g.ny);
   const int base = c.id - co * stride;
 #pragma unroll
   for (int m = 0; m < 6; ++m) {
-    int cm = co + m - 2;
+    int cm = co + m + first;
     cm += cm < 0 ? n : 0;
     cm -= cm >= n ? n : 0;
     idx[m] = base + cm * stride;
   }
+}
+
+// REC stencil of the +face along dir: cells at offsets -2..+3.
+__device__ __forceinline__ void stencil6(const GridDims& g, const Cell& c, int dir, int* idx) {
+  stencil6_from(g, c, dir, -2, idx);
+}
+
+// Sixth-order derivative at a centre of a quantity f_m stored at the +faces
+// (edges) at offsets m = -3..+2 along the direction, i.e. at -5/2..+5/2:
+// (-9 f_{-5/2} + 125 f_{-3/2} - 2250 f_{-1/2} + 2250 f_{1/2} - 125 f_{3/2}
+//  + 9 f_{5/2}) / 1920, times 1/dx by the caller.  This is the difference of
+// the corrected fluxes f - D2 f/24 + 3 D4 f/640 at the two faces (HO DER).
+__device__ __forceinline__ double der6(double f0, double f1, double f2, double f3, double f4,
+                                       double f5) {
+  return (2250.0 * (f3 - f2) - 125.0 * (f4 - f1) + 9.0 * (f5 - f0)) * (1.0 / 1920.0);
+}
+
+template <typename P>
+__device__ __forceinline__ double der6_at(const P* q, const int* s) {
+  return der6((double)q[s[0]], (double)q[s[1]], (double)q[s[2]], (double)q[s[3]],
+              (double)q[s[4]], (double)q[s[5]]);
 }
 
 // Index of the neighbour at offset -1 along dir (periodic).
@@ -101,6 +124,20 @@ __device__ __forceinline__ int plus1(const GridDims& g, const Cell& c, int dir) 
   if (dir == 0) return c.i == g.nx - 1 ? c.id - (g.nx - 1) : c.id + 1;
   if (dir == 1) return c.j == g.ny - 1 ? c.id - (g.ny - 1) * g.nx : c.id + g.nx;
   return c.k == g.nz - 1 ? c.id - (g.nz - 1) * g.nx * g.ny : c.id + g.nx * g.ny;
+}
+
+// INT: centred B_d of the cell from the face array bfd: the mean of the two
+// d-faces, or (ho) the sixth-order interpolation of the six nearest faces,
+// (3, -25, 150, 150, -25, 3)/256.
+__device__ __forceinline__ double centre_b(const GridDims& g, const Cell& c, const double* bfd,
+                                           int d, int ho) {
+  if (ho) {
+    int s[6];
+    stencil6_from(g, c, d, -3, s);
+    return (150.0 * (bfd[s[2]] + bfd[s[3]]) - 25.0 * (bfd[s[1]] + bfd[s[4]]) +
+            3.0 * (bfd[s[0]] + bfd[s[5]])) * (1.0 / 256.0);
+  }
+  return 0.5 * (bfd[minus1(g, c, d)] + bfd[c.id]);
 }
 
 __device__ __forceinline__ unsigned wave_sum_u32(unsigned v) {
@@ -154,11 +191,7 @@ __global__ __launch_bounds__(kThreads) void k_init(InitArgs a) {
   const Cell c = cell_of(a.g);
   if (!c.valid) return;
   double bc[3];
-  for (int d = 0; d < 3; ++d) {
-    const double bp = a.bf_in[d][c.id];
-    const double bm = a.bf_in[d][minus1(a.g, c, d)];
-    bc[d] = 0.5 * (bm + bp);
-  }
+  for (int d = 0; d < 3; ++d) bc[d] = centre_b(a.g, c, a.bf_in[d], d, a.ho);
   FaceState<double> s{a.prim5[0][c.id], a.prim5[1][c.id], a.prim5[2][c.id], a.prim5[3][c.id],
                       a.prim5[4][c.id], bc[0], bc[1], bc[2]};
   FaceEval<double> e;
@@ -305,7 +338,7 @@ __global__ __launch_bounds__(kThreads) void k_c2p(C2PArgs a) {
   double Wprev = 1.0;
   if (c.valid) {
     for (int n = 0; n < 5; ++n) u[n] = a.cons[n][c.id];
-    for (int d = 0; d < 3; ++d) b[d] = 0.5 * (a.bf[d][minus1(a.g, c, d)] + a.bf[d][c.id]);
+    for (int d = 0; d < 3; ++d) b[d] = centre_b(a.g, c, a.bf[d], d, a.ho);
     Wprev = a.guess == 2 ? -1.0 : a.W[c.id];
   }
   double pr[5];
@@ -404,7 +437,7 @@ __global__ __launch_bounds__(kThreads) void k_harvest(HarvestArgs a) {
   if (!(r < a.frac)) return;
   double u[5], b[3], pr[5];
   for (int n = 0; n < 5; ++n) u[n] = a.cons[n][c.id];
-  for (int d = 0; d < 3; ++d) b[d] = 0.5 * (a.bf[d][minus1(a.g, c, d)] + a.bf[d][c.id]);
+  for (int d = 0; d < 3; ++d) b[d] = centre_b(a.g, c, a.bf[d], d, a.ho);
   double W = a.W[c.id];
   int it = 0;
   bool fl = false;
@@ -444,7 +477,7 @@ void launch_harvest(const HarvestArgs& a, hipStream_t s) {
 template <int DIR>
 struct FluxTile : Tile<DIR == 2 ? 1 : 4, DIR == 2 ? 4 : 1> {};
 
-template <int DIR, typename TS, bool CFL, bool STATS>
+template <int DIR, typename TS, bool CFL, bool STATS, int REC>
 __global__ __launch_bounds__(FluxTile<DIR>::kThreads) void k_flux(FluxArgs<TS> a) {
   using T = TS;
   constexpr int T1 = (DIR + 1) % 3, T2 = (DIR + 2) % 3;
@@ -460,7 +493,10 @@ __global__ __launch_bounds__(FluxTile<DIR>::kThreads) void k_flux(FluxArgs<TS> a
     stencil6(a.g, c, DIR, idx);
     FaceState<T> L, R;
     auto rec = [&](const TS* q, T& l, T& r) {
-      mp5_pair<T>(q[idx[0]], q[idx[1]], q[idx[2]], q[idx[3]], q[idx[4]], q[idx[5]], l, r);
+      if (REC == kRecMc)  // the outer two stencil values are not read
+        rec_pair<REC, T>(T(0), q[idx[1]], q[idx[2]], q[idx[3]], q[idx[4]], T(0), l, r);
+      else
+        rec_pair<REC, T>(q[idx[0]], q[idx[1]], q[idx[2]], q[idx[3]], q[idx[4]], q[idx[5]], l, r);
     };
     rec(a.prim[0], L.rho, R.rho);
     rec(a.prim[1 + DIR], L.vn, R.vn);
@@ -543,10 +579,10 @@ __global__ __launch_bounds__(FluxTile<DIR>::kThreads) void k_flux(FluxArgs<TS> a
   }
 }
 
-template <typename TS>
-void launch_flux(int dir, const FluxArgs<TS>& a, bool cfl, bool stats, hipStream_t s) {
+template <typename TS, int REC>
+void launch_flux_rec(int dir, const FluxArgs<TS>& a, bool cfl, bool stats, hipStream_t s) {
 #define SRMHD_FLUX(D, C, S)                                                               \
-  hipLaunchKernelGGL((k_flux<D, TS, C, S>),                                               \
+  hipLaunchKernelGGL((k_flux<D, TS, C, S, REC>),                                          \
                      (tile_grid<FluxTile<D>::kY, FluxTile<D>::kZ>(a.g)),                  \
                      (tile_block<FluxTile<D>::kY, FluxTile<D>::kZ>()), 0, s, a)
   if (dir == 0) {
@@ -562,8 +598,15 @@ void launch_flux(int dir, const FluxArgs<TS>& a, bool cfl, bool stats, hipStream
   }
 #undef SRMHD_FLUX
 }
-template void launch_flux<double>(int, const FluxArgs<double>&, bool, bool, hipStream_t);
-template void launch_flux<float>(int, const FluxArgs<float>&, bool, bool, hipStream_t);
+
+template <typename TS>
+void launch_flux(int dir, const FluxArgs<TS>& a, bool cfl, bool stats, int rec, hipStream_t s) {
+  if (rec == kRecMc) launch_flux_rec<TS, kRecMc>(dir, a, cfl, stats, s);
+  else if (rec == kRecMp5Point) launch_flux_rec<TS, kRecMp5Point>(dir, a, cfl, stats, s);
+  else launch_flux_rec<TS, kRecMp5>(dir, a, cfl, stats, s);
+}
+template void launch_flux<double>(int, const FluxArgs<double>&, bool, bool, int, hipStream_t);
+template void launch_flux<float>(int, const FluxArgs<float>&, bool, bool, int, hipStream_t);
 
 // ------------------------------------------------------------------- UCT
 // Edge field E_K at (+1/2 along P, +1/2 along Q), (P, Q, K) cyclic, in FP64:
@@ -572,14 +615,18 @@ template void launch_flux<float>(int, const FluxArgs<float>&, bool, bool, hipStr
 // along P; E^{ab} = v_Q^{ab} B_P^b - v_P^{ab} B_Q^a (E = -v x B); edge speeds
 // are the maxima over the two adjacent faces of each direction.
 // One thread computes E_x, E_y and E_z of its cell.
-template <int K, typename TS>
+template <int K, int REC, typename TS>
 __device__ __forceinline__ double uct_one(const Uct3Args<TS>& a, int id, const int* const* st) {
   constexpr int P = (K + 1) % 3, Q = (K + 2) % 3;
   const int* iq = st[Q];
   const int* ip = st[P];
   auto rec = [&](auto q, const int* idx, double& l, double& r) {
-    mp5_pair<double>((double)q[idx[0]], (double)q[idx[1]], (double)q[idx[2]],
-                     (double)q[idx[3]], (double)q[idx[4]], (double)q[idx[5]], l, r);
+    if (REC == kRecMc)  // the outer two stencil values are not read
+      rec_pair<REC, double>(0.0, (double)q[idx[1]], (double)q[idx[2]], (double)q[idx[3]],
+                            (double)q[idx[4]], 0.0, l, r);
+    else
+      rec_pair<REC, double>((double)q[idx[0]], (double)q[idx[1]], (double)q[idx[2]],
+                            (double)q[idx[3]], (double)q[idx[4]], (double)q[idx[5]], l, r);
   };
   double vp[2][2], vq[2][2];
 #pragma unroll
@@ -608,7 +655,7 @@ __device__ __forceinline__ double uct_one(const Uct3Args<TS>& a, int id, const i
 // fast as 64x2x2 and faster than 64x4x4.
 using UctTile = Tile<4, 1>;
 
-template <typename TS>
+template <typename TS, int REC>
 __global__ __launch_bounds__(UctTile::kThreads) void k_uct3(Uct3Args<TS> a) {
   const Cell c = cell_of_tile<UctTile::kY, UctTile::kZ>(a.g);
   if (!c.valid) return;
@@ -617,49 +664,70 @@ __global__ __launch_bounds__(UctTile::kThreads) void k_uct3(Uct3Args<TS> a) {
   stencil6(a.g, c, 1, sy);
   stencil6(a.g, c, 2, sz);
   const int* st[3] = {sx, sy, sz};
-  a.e[2][c.id] = uct_one<2>(a, c.id, st);
-  a.e[0][c.id] = uct_one<0>(a, c.id, st);
-  a.e[1][c.id] = uct_one<1>(a, c.id, st);
+  a.e[2][c.id] = uct_one<2, REC>(a, c.id, st);
+  a.e[0][c.id] = uct_one<0, REC>(a, c.id, st);
+  a.e[1][c.id] = uct_one<1, REC>(a, c.id, st);
 }
 
 template <typename TS>
-void launch_uct3(const Uct3Args<TS>& a, hipStream_t s) {
-  hipLaunchKernelGGL((k_uct3<TS>), (tile_grid<UctTile::kY, UctTile::kZ>(a.g)),
-                     (tile_block<UctTile::kY, UctTile::kZ>()), 0, s, a);
+void launch_uct3(const Uct3Args<TS>& a, int rec, hipStream_t s) {
+  const dim3 grid = tile_grid<UctTile::kY, UctTile::kZ>(a.g);
+  const dim3 blk = tile_block<UctTile::kY, UctTile::kZ>();
+  if (rec == kRecMc) hipLaunchKernelGGL((k_uct3<TS, kRecMc>), grid, blk, 0, s, a);
+  else if (rec == kRecMp5Point) hipLaunchKernelGGL((k_uct3<TS, kRecMp5Point>), grid, blk, 0, s, a);
+  else hipLaunchKernelGGL((k_uct3<TS, kRecMp5>), grid, blk, 0, s, a);
 }
-template void launch_uct3<double>(const Uct3Args<double>&, hipStream_t);
-template void launch_uct3<float>(const Uct3Args<float>&, hipStream_t);
+template void launch_uct3<double>(const Uct3Args<double>&, int, hipStream_t);
+template void launch_uct3<float>(const Uct3Args<float>&, int, hipStream_t);
 
-// -------------------------------------------------- DER + RK3 stage update
+// -------------------------------------------------- DER + RK stage update
 // L(U) at centres: -sum_d (Fhat(+d face) - Fhat(-d face))/dx_d; at faces:
-// dB_d/dt = -(d_p E_q - d_q E_p), (d, p, q) cyclic.  SSP-RK3 (Shu & Osher):
-// stage 1: U1 = U^n + dt L(U^n); stage 2: U2 = 3/4 U^n + 1/4 (U1 + dt L(U1));
-// stage 3: U^{n+1} = 1/3 U^n + 2/3 (U2 + dt L(U2)).  Stage 0 writes L only.
-// Stage 1 writes U1 to a work register, so U^n stays in the caller's arrays
-// and is read back by stages 2 and 3 (no copy of U^n).
-template <int STAGE, typename TS>
+// dB_d/dt = -(d_p E_q - d_q E_p), (d, p, q) cyclic.  HO: the sixth-order
+// differences (der6) of the face fluxes and edge fields instead.  SSP-RK3
+// (Shu & Osher): stage 1: U1 = U^n + dt L(U^n); stage 2: U2 = 3/4 U^n +
+// 1/4 (U1 + dt L(U1)); stage 3: U^{n+1} = 1/3 U^n + 2/3 (U2 + dt L(U2)).
+// SSP-RK2: stage 1, then stage 4: U^{n+1} = 1/2 U^n + 1/2 (U1 + dt L(U1)).
+// Stage 0 writes L only.  Stage 1 writes U1 to a work register, so U^n stays
+// in the caller's arrays and is read back by the later stages (no copy).
+template <int STAGE, typename TS, bool HO>
 __global__ __launch_bounds__(kThreads) void k_update(UpdArgs<TS> a) {
   const Cell c = cell_of(a.g);
   if (!c.valid) return;
-  const int im = minus1(a.g, c, 0), jm = minus1(a.g, c, 1), km = minus1(a.g, c, 2);
-  const int nb[3] = {im, jm, km};
   const double* ix = a.g.inv_dx;
-  double r[8];
-#pragma unroll
-  for (int n = 0; n < 5; ++n) {
-    double s = 0.0;
-#pragma unroll
-    for (int d = 0; d < 3; ++d)
-      s += ((double)a.fhat[d][n][c.id] - (double)a.fhat[d][n][nb[d]]) * ix[d];
-    r[n] = -s;
-  }
   const double* Ex = a.e[0];
   const double* Ey = a.e[1];
   const double* Ez = a.e[2];
-  const double ex0 = Ex[c.id], ey0 = Ey[c.id], ez0 = Ez[c.id];
-  r[5] = -((ez0 - Ez[jm]) * ix[1] - (ey0 - Ey[km]) * ix[2]);
-  r[6] = -((ex0 - Ex[km]) * ix[2] - (ez0 - Ez[im]) * ix[0]);
-  r[7] = -((ey0 - Ey[im]) * ix[0] - (ex0 - Ex[jm]) * ix[1]);
+  double r[8];
+  if (HO) {
+    int s[3][6];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) stencil6_from(a.g, c, d, -3, s[d]);
+#pragma unroll
+    for (int n = 0; n < 5; ++n) {
+      double acc = 0.0;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) acc += der6_at(a.fhat[d][n], s[d]) * ix[d];
+      r[n] = -acc;
+    }
+    r[5] = -(der6_at(Ez, s[1]) * ix[1] - der6_at(Ey, s[2]) * ix[2]);
+    r[6] = -(der6_at(Ex, s[2]) * ix[2] - der6_at(Ez, s[0]) * ix[0]);
+    r[7] = -(der6_at(Ey, s[0]) * ix[0] - der6_at(Ex, s[1]) * ix[1]);
+  } else {
+    const int im = minus1(a.g, c, 0), jm = minus1(a.g, c, 1), km = minus1(a.g, c, 2);
+    const int nb[3] = {im, jm, km};
+#pragma unroll
+    for (int n = 0; n < 5; ++n) {
+      double acc = 0.0;
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+        acc += ((double)a.fhat[d][n][c.id] - (double)a.fhat[d][n][nb[d]]) * ix[d];
+      r[n] = -acc;
+    }
+    const double ex0 = Ex[c.id], ey0 = Ey[c.id], ez0 = Ez[c.id];
+    r[5] = -((ez0 - Ez[jm]) * ix[1] - (ey0 - Ey[km]) * ix[2]);
+    r[6] = -((ex0 - Ex[km]) * ix[2] - (ez0 - Ez[im]) * ix[0]);
+    r[7] = -((ey0 - Ey[im]) * ix[0] - (ex0 - Ex[jm]) * ix[1]);
+  }
   if (STAGE == 0) {
 #pragma unroll
     for (int n = 0; n < 8; ++n) a.rhs_out[n][c.id] = r[n];
@@ -673,25 +741,34 @@ __global__ __launch_bounds__(kThreads) void k_update(UpdArgs<TS> a) {
       a.uout[n][c.id] = u + dt * r[n];
     } else if (STAGE == 2) {
       a.uout[n][c.id] = 0.75 * a.u0[n][c.id] + 0.25 * (u + dt * r[n]);
-    } else {
+    } else if (STAGE == 3) {
       a.uout[n][c.id] = (1.0 / 3.0) * a.u0[n][c.id] + (2.0 / 3.0) * (u + dt * r[n]);
+    } else {
+      a.uout[n][c.id] = 0.5 * a.u0[n][c.id] + 0.5 * (u + dt * r[n]);
     }
   }
 }
 
-template <typename TS>
-void launch_update(int stage, const UpdArgs<TS>& a, hipStream_t s) {
+template <typename TS, bool HO>
+void launch_update_ho(int stage, const UpdArgs<TS>& a, hipStream_t s) {
   const dim3 grid = cell_grid(a.g);
   dim3 blk(kBlockX, kBlockY);
   switch (stage) {
-    case 0: hipLaunchKernelGGL((k_update<0, TS>), grid, blk, 0, s, a); break;
-    case 1: hipLaunchKernelGGL((k_update<1, TS>), grid, blk, 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_update<2, TS>), grid, blk, 0, s, a); break;
-    default: hipLaunchKernelGGL((k_update<3, TS>), grid, blk, 0, s, a); break;
+    case 0: hipLaunchKernelGGL((k_update<0, TS, HO>), grid, blk, 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_update<1, TS, HO>), grid, blk, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_update<2, TS, HO>), grid, blk, 0, s, a); break;
+    case 3: hipLaunchKernelGGL((k_update<3, TS, HO>), grid, blk, 0, s, a); break;
+    default: hipLaunchKernelGGL((k_update<4, TS, HO>), grid, blk, 0, s, a); break;
   }
 }
-template void launch_update<double>(int, const UpdArgs<double>&, hipStream_t);
-template void launch_update<float>(int, const UpdArgs<float>&, hipStream_t);
+
+template <typename TS>
+void launch_update(int stage, const UpdArgs<TS>& a, bool ho, hipStream_t s) {
+  if (ho) launch_update_ho<TS, true>(stage, a, s);
+  else launch_update_ho<TS, false>(stage, a, s);
+}
+template void launch_update<double>(int, const UpdArgs<double>&, bool, hipStream_t);
+template void launch_update<float>(int, const UpdArgs<float>&, bool, hipStream_t);
 
 // ------------------------------------------------------------ timestep
 // dt = cfl / amax (or dt_fixed) once per step, from the first stage's speeds;
@@ -754,13 +831,22 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce_partial(ReduceArgs a)
     const int id = (int)q;
     for (int n = 0; n < 8; ++n) acc[n] += a.a[n][id];
     const int i = id % a.g.nx, j = (id / a.g.nx) % a.g.ny, k = id / nxy;
-    const int im = i == 0 ? id + a.g.nx - 1 : id - 1;
-    const int jm = j == 0 ? id + (a.g.ny - 1) * a.g.nx : id - a.g.nx;
-    const int km = k == 0 ? id + (a.g.nz - 1) * nxy : id - nxy;
     double dv = 0.0;
-    dv += (a.bf[0][id] - a.bf[0][im]) * a.g.inv_dx[0];
-    dv += (a.bf[1][id] - a.bf[1][jm]) * a.g.inv_dx[1];
-    dv += (a.bf[2][id] - a.bf[2][km]) * a.g.inv_dx[2];
+    if (a.ho) {
+      const Cell c{i, j, k, id, true};
+      int s[6];
+      for (int d = 0; d < 3; ++d) {
+        stencil6_from(a.g, c, d, -3, s);
+        dv += der6_at(a.bf[d], s) * a.g.inv_dx[d];
+      }
+    } else {
+      const int im = i == 0 ? id + a.g.nx - 1 : id - 1;
+      const int jm = j == 0 ? id + (a.g.ny - 1) * a.g.nx : id - a.g.nx;
+      const int km = k == 0 ? id + (a.g.nz - 1) * nxy : id - nxy;
+      dv += (a.bf[0][id] - a.bf[0][im]) * a.g.inv_dx[0];
+      dv += (a.bf[1][id] - a.bf[1][jm]) * a.g.inv_dx[1];
+      dv += (a.bf[2][id] - a.bf[2][km]) * a.g.inv_dx[2];
+    }
     acc[8] = fmax(acc[8], fabs(dv));
   }
   for (int n = 0; n < 9; ++n) sm[n][threadIdx.x] = acc[n];

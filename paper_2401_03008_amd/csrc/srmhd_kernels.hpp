@@ -9,6 +9,10 @@
 
 namespace srmhd {
 
+// Reconstruction kernels: MP5 on the cell-average kernel, linear with the MC
+// limiter, MP5 around the point-value interpolation (HO scheme).
+constexpr int kRecMp5 = 0, kRecMc = 1, kRecMp5Point = 2;
+
 constexpr int kBlockX = 64;  // one wavefront along x
 constexpr int kBlockY = 4;   // four wavefronts per workgroup
 constexpr int kThreads = kBlockX * kBlockY;
@@ -55,6 +59,7 @@ struct C2PArgs {
   double gam, tol, pfloor;
   int maxit;
   int guess;  // 0 = previous W, 1 = learned guess (fallback previous W), 2 = cold start
+  int ho;     // 1: sixth-order INT of the face B
   MlpDev mlp;
   unsigned long long* counters;
   unsigned int* err;
@@ -73,6 +78,7 @@ struct HarvestArgs {
   unsigned int* count;
   double frac;
   unsigned int seed;
+  int ho;
 };
 
 template <typename TS>
@@ -124,6 +130,7 @@ struct InitArgs {
   double* bf[3];
   double* W;
   double gam;
+  int ho;
 };
 
 struct ReduceArgs {
@@ -133,18 +140,22 @@ struct ReduceArgs {
   double* partial;  // [nblocks][9]
   int nblocks;
   DevScalars* sc;
+  int ho;  // 1: div B with the sixth-order differences
 };
 
 // Launchers (srmhd_kernels.hip).  All asynchronous on `stream`.
 void launch_init(const InitArgs& a, hipStream_t s);
 void launch_c2p(const C2PArgs& a, bool stats, hipStream_t s);
 void launch_harvest(const HarvestArgs& a, hipStream_t s);
+// rec: kRecMp5, kRecMc or kRecMp5Point (srmhd_phys.hpp).  Update stages: 0 =
+// L(U) only, 1..3 = SSP-RK3 stages, 4 = second (last) SSP-RK2 stage; ho:
+// sixth-order DER.
 template <typename TS>
-void launch_flux(int dir, const FluxArgs<TS>& a, bool cfl, bool stats, hipStream_t s);
+void launch_flux(int dir, const FluxArgs<TS>& a, bool cfl, bool stats, int rec, hipStream_t s);
 template <typename TS>
-void launch_uct3(const Uct3Args<TS>& a, hipStream_t s);
+void launch_uct3(const Uct3Args<TS>& a, int rec, hipStream_t s);
 template <typename TS>
-void launch_update(int stage, const UpdArgs<TS>& a, hipStream_t s);
+void launch_update(int stage, const UpdArgs<TS>& a, bool ho, hipStream_t s);
 void launch_dt(DevScalars* sc, double cfl, double dt_fixed, hipStream_t s);
 void launch_zero_u64(unsigned long long* p, size_t n, hipStream_t s);
 void launch_set_time(DevScalars* sc, double t, long long step, hipStream_t s);

@@ -11,6 +11,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "srmhd_kernels.hpp"
+
 namespace srmhd {
 
 // Primitive state in a face-normal frame: n is the face normal, (n, t1, t2)
@@ -140,15 +142,26 @@ __device__ __forceinline__ T mp5(T vm2, T vm1, T v0, T vp1, T vp2) {
 // mp5(s0..s4), right = mp5(s5..s1).  Same arithmetic as two mp5 calls, but
 // the curvatures d_i, d_{i+1} and d^{M4}_{i+1/2} (minmod4 is symmetric in its
 // pair) are computed once for both sides, and only when a side needs its
-// limiter.
-template <typename T>
+// limiter.  POINT: the unlimited value is the fifth-order interpolation of
+// point values, (3, -20, 90, 60, -5)/128 (the face point values that the
+// sixth-order DER expects), instead of the cell-average kernel.
+template <typename T, bool POINT = false>
 __device__ __forceinline__ void mp5_pair(T s0, T s1, T s2, T s3, T s4, T s5, T& left, T& right) {
-  const T c60 = T(1.0 / 60.0);
   // left: centre s2; right: centre s3, mirrored
-  const T vorL = s2 + (T(2) * (s0 - s2) - T(13) * (s1 - s2) + T(27) * (s3 - s2) -
-                       T(3) * (s4 - s2)) * c60;
-  const T vorR = s3 + (T(2) * (s5 - s3) - T(13) * (s4 - s3) + T(27) * (s2 - s3) -
-                       T(3) * (s1 - s3)) * c60;
+  T vorL, vorR;
+  if (POINT) {
+    const T c128 = T(1.0 / 128.0);
+    vorL = s2 + (T(3) * (s0 - s2) - T(20) * (s1 - s2) + T(60) * (s3 - s2) -
+                 T(5) * (s4 - s2)) * c128;
+    vorR = s3 + (T(3) * (s5 - s3) - T(20) * (s4 - s3) + T(60) * (s2 - s3) -
+                 T(5) * (s1 - s3)) * c128;
+  } else {
+    const T c60 = T(1.0 / 60.0);
+    vorL = s2 + (T(2) * (s0 - s2) - T(13) * (s1 - s2) + T(27) * (s3 - s2) -
+                 T(3) * (s4 - s2)) * c60;
+    vorR = s3 + (T(2) * (s5 - s3) - T(13) * (s4 - s3) + T(27) * (s2 - s3) -
+                 T(3) * (s1 - s3)) * c60;
+  }
   const T dlL = s2 - s1, dlR = s3 - s4;
   const T vmpL = s2 + minmod2(s3 - s2, T(4) * dlL);
   const T vmpR = s3 + minmod2(s2 - s3, T(4) * dlR);
@@ -179,6 +192,28 @@ __device__ __forceinline__ void mp5_pair(T s0, T s1, T s2, T s3, T s4, T s5, T& 
     const T vmin = fmax(fmin(fmin(s3, s2), vmd), fmin(fmin(s3, vul), vlc));
     const T vmax = fmin(fmax(fmax(s3, s2), vmd), fmax(fmax(s3, vul), vlc));
     right = vorR + minmod2(vmin - vorR, vmax - vorR);
+  }
+}
+
+// Monotonized-central slope (van Leer 1977): sign(a) min(2|a|, 2|b|, |a+b|/2)
+// when a and b have the same sign, else 0.
+template <typename T>
+__device__ __forceinline__ T mc_slope(T a, T b) {
+  const T m = fmin(fmin(T(2) * fabs(a), T(2) * fabs(b)), T(0.5) * fabs(a + b));
+  return a * b > T(0) ? copysign(m, a) : T(0);
+}
+
+// REC of both states at x_{i+1/2} from v_{i-2..i+3}.  kRecMp5: MP5 (cell-
+// average kernel); kRecMc: linear, v_i + MC/2 and v_{i+1} - MC/2 (uses
+// v_{i-1..i+2} only); kRecMp5Point: MP5 around the point-value interpolation.
+
+template <int REC, typename T>
+__device__ __forceinline__ void rec_pair(T s0, T s1, T s2, T s3, T s4, T s5, T& left, T& right) {
+  if (REC == kRecMc) {
+    left = s2 + T(0.5) * mc_slope(s2 - s1, s3 - s2);
+    right = s3 - T(0.5) * mc_slope(s3 - s2, s4 - s3);
+  } else {
+    mp5_pair<T, REC == kRecMp5Point>(s0, s1, s2, s3, s4, s5, left, right);
   }
 }
 

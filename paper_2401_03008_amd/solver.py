@@ -15,13 +15,14 @@ from . import binding as B
 _PREC = {"fp64": B.SRMHD_FP64, "mixed": B.SRMHD_MIXED}
 _RIEM = {"hll": B.SRMHD_HLL, "llf": B.SRMHD_LLF}
 _GUESS = {"prev": B.SRMHD_GUESS_PREV, "mlp": B.SRMHD_GUESS_MLP, "cold": B.SRMHD_GUESS_COLD}
+_REC = {"mp5": B.SRMHD_REC_MP5, "mc": B.SRMHD_REC_MC}
 
 
 class Solver:
     def __init__(self, nx, ny=None, nz=None, L=(1.0, 1.0, 1.0), gamma_ad=4.0 / 3.0, cfl=0.5,
                  dt_fixed=0.0, riemann="hll", precision="fp64", guess="prev",
                  newton_maxit=50, newton_tol=1e-14, pfloor=0.0, collect_stats=True,
-                 device="cuda:0", stream=None):
+                 recon="mp5", time_order=3, high_order=False, device="cuda:0", stream=None):
         if not torch.cuda.is_available():
             raise RuntimeError("Solver needs a HIP device (torch.cuda.is_available() is False)")
         ny = nx if ny is None else ny
@@ -36,6 +37,9 @@ class Solver:
         cfg.guess = _GUESS[guess]
         cfg.newton_maxit, cfg.newton_tol, cfg.pfloor = newton_maxit, newton_tol, pfloor
         cfg.collect_stats = 1 if collect_stats else 0
+        cfg.recon = _REC[recon]
+        cfg.time_order = int(time_order)
+        cfg.high_order = 1 if high_order else 0
         self.cfg = cfg
         self.shape = (nz, ny, nx)
         wb = B.srmhd_work_bytes(cfg)
