@@ -59,7 +59,8 @@ enum { SRMHD_REC_MP5 = 0, SRMHD_REC_MC = 1 };
 #define SRMHD_ERRBIT_PRESSURE 8u  /* recovered p <= 0 with no floor set */
 
 typedef struct {
-  int nx, ny, nz;   /* cells per direction, each >= 8; nx*ny*nz < 2^31 */
+  int nx, ny, nz;   /* cells per direction, each >= 1 (1 makes a uniform
+                       direction: a 2D or 1D box); nx*ny*nz < 2^31 */
   double lx, ly, lz;/* box lengths (> 0) */
   double gamma_ad;  /* adiabatic index, 1 < gamma_ad <= 2 (4/3 in all tests) */
   double cfl;       /* dt = cfl / max_cells sum_d max(a+,a-)_d/dx_d */
@@ -209,8 +210,9 @@ int srmhd_get_kernel_times(srmhd_ctx *ctx, double *ms, long *launches);
 #define SRMHD_MLP_OFF_B3 4672
 
 /* Use the network (device params: FP32 biases and BF16 weights, caller-owned,
- * kept by pointer) for the guess.  norm (host, 14 floats): feature means[5],
- * feature std[5], output means[2], output std[2].  Asynchronous. */
+ * kept by pointer; w_bf16 8-byte aligned, else SRMHD_E_INVAL) for the guess.
+ * norm (host, 14 floats): feature means[5], feature std[5], output means[2],
+ * output std[2].  Asynchronous. */
 int srmhd_set_mlp(srmhd_ctx *ctx, const float *params, const uint16_t *w_bf16,
                   const float *norm);
 

@@ -101,7 +101,7 @@ struct KTimer {
 
 std::string validate(const srmhd_config* c) {
   if (!c) return "config is NULL";
-  if (c->nx < 8 || c->ny < 8 || c->nz < 8) return "nx, ny, nz must each be >= 8";
+  if (c->nx < 1 || c->ny < 1 || c->nz < 1) return "nx, ny, nz must each be >= 1";
   if ((long long)c->nx * c->ny * c->nz >= (1LL << 31)) return "nx*ny*nz must be < 2^31";
   if (c->nz > 65535 || (c->ny + kBlockY - 1) / kBlockY > 65535) return "grid too tall";
   if (!(c->lx > 0 && c->ly > 0 && c->lz > 0)) return "box lengths must be > 0";
@@ -557,6 +557,8 @@ int srmhd_set_time(srmhd_ctx* c, double t, long step) {
 int srmhd_set_mlp(srmhd_ctx* c, const float* params, const uint16_t* w_bf16, const float* norm) {
   if (!c) return SRMHD_E_INVAL;
   if (!params || !w_bf16 || !norm) return fail(c, SRMHD_E_INVAL, "params/w_bf16/norm is NULL");
+  if (reinterpret_cast<uintptr_t>(w_bf16) % 8 != 0)
+    return fail(c, SRMHD_E_INVAL, "w_bf16 must be 8-byte aligned");
   MlpDev m;
   m.w = w_bf16;
   m.p = params;

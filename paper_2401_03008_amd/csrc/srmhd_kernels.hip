@@ -75,20 +75,26 @@ inline dim3 cell_grid(const GridDims& g) { return tile_grid<kBlockY, 1>(g); }
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x; }
 
-// Stencil indices along direction dir at offsets first..first+5 (periodic;
-// first >= -3 and the grid has >= 8 cells per direction).
+// Stencil indices along direction dir at offsets first..first+5 (periodic,
+// first >= -3).  A direction with fewer than 4 cells (a 2D or 1D box: the
+// stencil wraps more than once) takes the general modulo.
 __device__ __forceinline__ void stencil6_from(const GridDims& g, const Cell& c, int dir,
                                               int first, int* idx) {
   const int n = dir == 0 ? g.nx : (dir == 1 ? g.ny : g.nz);
   const int co = dir == 0 ? c.i : (dir == 1 ? c.j : c.k);
   const int stride = dir == 0 ? 1 : (dir == 1 ? g.nx : g.nx * g.ny);
   const int base = c.id - co * stride;
+  if (n >= 4) {
 #pragma unroll
-  for (int m = 0; m < 6; ++m) {
-    int cm = co + m + first;
-    cm += cm < 0 ? n : 0;
-    cm -= cm >= n ? n : 0;
-    idx[m] = base + cm * stride;
+    for (int m = 0; m < 6; ++m) {
+      int cm = co + m + first;
+      cm += cm < 0 ? n : 0;
+      cm -= cm >= n ? n : 0;
+      idx[m] = base + cm * stride;
+    }
+  } else {
+#pragma unroll
+    for (int m = 0; m < 6; ++m) idx[m] = base + ((co + m + first + 3 * n) % n) * stride;
   }
 }
 
@@ -326,7 +332,7 @@ __device__ int con2prim(const double* u, double bx, double by, double bz, double
 template <bool STATS, bool MLP>
 __global__ __launch_bounds__(kThreads) void k_c2p(C2PArgs a) {
   __shared__ unsigned s_cnt[CNT_N];
-  __shared__ uint16_t s_lx[MLP ? kBlockY * 64 * 16 : 1];
+  __shared__ __align__(16) uint16_t s_lx[MLP ? kBlockY * 64 * 16 : 4];
   __shared__ float s_ly[MLP ? kBlockY * 128 : 1];
   BlockCounters bc;
   if (STATS) bc.init(s_cnt);
@@ -347,21 +353,17 @@ __global__ __launch_bounds__(kThreads) void k_c2p(C2PArgs a) {
     const double S2 = u[1] * u[1] + u[2] * u[2] + u[3] * u[3];
     const double B2 = b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
     const double tau = u[1] * b[0] + u[2] * b[1] + u[3] * b[2];
-    double fd[kMlpIn];
-    mlp_features(u[0], S2, B2, tau, u[4], fd);
     float fe[kMlpIn];
+    mlp_features_f32(u[0], S2, B2, tau, u[4], fe);
     bool fin = true;
-    for (int k = 0; k < kMlpIn; ++k) {
-      fe[k] = (float)fd[k];
-      fin = fin && isfinite(fe[k]);
-    }
+    for (int k = 0; k < kMlpIn; ++k) fin = fin && isfinite(fe[k]);
     if (!fin)
       for (int k = 0; k < kMlpIn; ++k) fe[k] = 0.f;
     float out[kMlpOut];
     mlp_wave(a.mlp, fe, &s_lx[threadIdx.y * 64 * 16], &s_ly[threadIdx.y * 128], out,
              []() { __syncthreads(); });
-    const double lor = exp(fmax((double)out[1], 0.0));
-    const double pg = u[0] * exp((double)out[0]);
+    const double lor = (double)__expf(fmaxf(out[1], 0.f));
+    const double pg = u[0] * (double)__expf(out[0]);
     W = fin ? u[0] * lor + a.gam / (a.gam - 1.0) * pg * lor * lor : -1.0;
     if (c.valid) {
       rc = con2prim(u, b[0], b[1], b[2], a.gam, W, a.maxit, a.tol, a.pfloor, pr, iters, floored,

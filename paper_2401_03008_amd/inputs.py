@@ -192,3 +192,87 @@ def turbulence(n, sigma0=10.0, beta0=0.1, B0=1.0, nmodes=16, kmax=2, gamma_max=5
     p0 = 0.5 * beta0 * B0 * B0
     prim5 = [full(rho0), cont(ux / lor), cont(uy / lor), zeros(), full(p0)]
     return prim5, [cont(bx), cont(by), full(B0)]
+
+
+def turbulence2d_modes(kmax=4):
+    """Wave vectors (kx, ky) of the 2D set-up (Sec. 5): kx in 0..kmax, ky in
+    -kmax..kmax, 1 <= |k| <= kmax (the disk of radius kmax), one of each +-k
+    pair (kx = 0 keeps ky > 0)."""
+    out = []
+    for a in range(0, kmax + 1):
+        for b in range(-kmax, kmax + 1):
+            if (a == 0 and b <= 0) or a * a + b * b > kmax * kmax:
+                continue
+            out.append((a, b))
+    return out
+
+
+def turbulence2d(n, rho0=1.0, sigma0=100.0, beta0=1.0, eta_rms=0.25, kmax=4, seed=20240103,
+                 device=None):
+    """The 2D (2.5D) Alfvenic turbulence set-up of Sec. 5 on an n x n x 1 box
+    of side 2 pi (the z direction uniform, depth 2 pi): static homogeneous
+    rho0, B0 = sqrt(sigma0 rho0) along z, p0 = beta0 B0^2 / 2, plus in-plane
+    fluctuations dv = A_v sum (k x z)/k cos(k.x + phi_v(k)) and
+    dB = A_B sum (k x z)/k cos(k.x + phi_B(k)) over turbulence2d_modes(kmax),
+    with independent uniform random phases (numpy default_rng(seed); the
+    paper's phases are not published).  dB is the discrete curl of the edge
+    potential A_z = A_B sum sin(k.x + phi_B)/k, so div B vanishes to
+    round-off.  The amplitudes are fixed a posteriori so that the box means
+    <|dv|>/v_A and <|dB|>/B0 (dB at the centres, face averages) equal eta_rms,
+    with v_A = B0 / sqrt(rho0 + 4 p0 + B0^2) (gamma = 4/3).
+
+    Returns (prim5, bf, L): numpy arrays (or torch float64 tensors on
+    `device`) of shape (1, n, n) and the box lengths (2 pi, 2 pi, 2 pi)."""
+    modes = turbulence2d_modes(kmax)
+    rng = np.random.default_rng(seed)
+    phiv = rng.uniform(0, 2 * math.pi, len(modes))
+    phiB = rng.uniform(0, 2 * math.pi, len(modes))
+    L = 2 * math.pi
+    h = L / n
+    if device is None:
+        xp = np
+        ar = lambda o: (np.arange(n) + o) * h
+        mesh = lambda a, b: np.meshgrid(a, b, indexing="ij")
+        zeros = lambda: np.zeros((1, n, n))
+        roll = lambda a, ax: np.roll(a, 1, axis=ax)
+        mean = lambda a: float(a.mean())
+    else:
+        import torch
+        xp = torch
+        ar = lambda o: (torch.arange(n, dtype=torch.float64, device=device) + o) * h
+        mesh = lambda a, b: torch.meshgrid(a, b, indexing="ij")
+        zeros = lambda: torch.zeros((1, n, n), dtype=torch.float64, device=device)
+        roll = lambda a, ax: torch.roll(a, 1, dims=ax)
+        mean = lambda a: float(a.mean().item())
+    Yc, Xc = mesh(ar(0.5), ar(0.5))
+    Ye, Xe = mesh(ar(1.0), ar(1.0))
+    A, vx, vy = zeros(), zeros(), zeros()
+    for (a, b), pv, pb in zip(modes, phiv, phiB):
+        k = math.hypot(a, b)
+        A[0] += xp.sin(a * Xe + b * Ye + float(pb)) / k
+        c = xp.cos(a * Xc + b * Yc + float(pv))
+        vx[0] += (b / k) * c
+        vy[0] -= (a / k) * c
+    del Xc, Yc, Xe, Ye
+    # face B from the discrete curl of A_z at (x_{i+1/2}, y_{j+1/2})
+    bx = (A - roll(A, 1)) / h
+    by = -(A - roll(A, 2)) / h
+    del A
+    B0 = math.sqrt(sigma0 * rho0)
+    p0 = 0.5 * beta0 * B0 * B0
+    va = B0 / math.sqrt(rho0 + 4.0 * p0 + B0 * B0)
+    bxc = 0.5 * (bx + roll(bx, 2))
+    byc = 0.5 * (by + roll(by, 1))
+    sB = eta_rms * B0 / mean(xp.sqrt(bxc ** 2 + byc ** 2))
+    sv = eta_rms * va / mean(xp.sqrt(vx ** 2 + vy ** 2))
+    del bxc, byc
+    full = lambda v: zeros() + float(v)
+    prim5 = [full(rho0), vx * sv, vy * sv, zeros(), full(p0)]
+    bf = [bx * sB, by * sB, full(B0)]
+    if device is None:
+        prim5 = [np.ascontiguousarray(q) for q in prim5]
+        bf = [np.ascontiguousarray(q) for q in bf]
+    else:
+        prim5 = [q.contiguous() for q in prim5]
+        bf = [q.contiguous() for q in bf]
+    return prim5, bf, (L, L, L)

@@ -16,30 +16,37 @@ from . import inputs
 from .solver import Solver
 
 
-def shell_spectrum(fields, nbins=None):
+def shell_spectrum(fields, nbins=None, groups=4096):
     """E(k) = sum over |k| in [k - 1/2, k + 1/2) of |FFT(f)|^2 / N^2, summed
     over the components in `fields` (list of (nz, ny, nx) tensors); k in units
-    of the box wave number."""
+    of the box wave number.  The shell sums are accumulated into `groups`
+    interleaved copies of the bins (mode index mod groups) and then added,
+    so that no bin takes more than ~N/groups atomic additions."""
     nz, ny, nx = fields[0].shape
-    kx = torch.fft.rfftfreq(nx, d=1.0 / nx, device=fields[0].device)
-    ky = torch.fft.fftfreq(ny, d=1.0 / ny, device=fields[0].device)
-    kz = torch.fft.fftfreq(nz, d=1.0 / nz, device=fields[0].device)
+    dev = fields[0].device
+    kx = torch.fft.rfftfreq(nx, d=1.0 / nx, device=dev)
+    ky = torch.fft.fftfreq(ny, d=1.0 / ny, device=dev)
+    kz = torch.fft.fftfreq(nz, d=1.0 / nz, device=dev)
+    nbins = nbins or int(min(m for m in (nx, ny, nz) if m > 1) // 2)
     K = torch.sqrt(kz[:, None, None] ** 2 + ky[None, :, None] ** 2 + kx[None, None, :] ** 2)
-    nbins = nbins or int(min(nx, ny, nz) // 2)
-    shell = torch.round(K).long().clamp(max=nbins)
+    gid = torch.round(K).long().clamp_(max=nbins).reshape(-1)
+    del K
+    gid.add_(torch.arange(gid.numel(), device=dev).remainder_(groups).mul_(nbins + 1))
     # rfft keeps half the x spectrum: weight the doubled modes
-    w = torch.full((nx // 2 + 1,), 2.0, device=K.device, dtype=torch.float64)
+    w = torch.full((nx // 2 + 1,), 2.0, device=dev, dtype=torch.float64)
     w[0] = 1.0
     if nx % 2 == 0:
         w[-1] = 1.0
     N = float(nx * ny * nz)
-    E = torch.zeros(nbins + 1, dtype=torch.float64, device=K.device)
+    E = torch.zeros(groups * (nbins + 1), dtype=torch.float64, device=dev)
     for f in fields:
         F = torch.fft.rfftn(f - f.mean())
         P = (F.real ** 2 + F.imag ** 2) * w[None, None, :] / (N * N)
-        E.index_add_(0, shell.reshape(-1), P.reshape(-1))
-        del F, P
-    return E[1:nbins].cpu()
+        del F
+        E.index_add_(0, gid, P.reshape(-1))
+        del P
+    del gid
+    return E.view(groups, nbins + 1).sum(0)[1:nbins].cpu()
 
 
 def turbulence_run(n, steps, precision="fp64", mlp=None, sigma0=10.0, gamma_max=5.0,
@@ -99,6 +106,66 @@ def turbulence_run(n, steps, precision="fp64", mlp=None, sigma0=10.0, gamma_max=
     return log
 
 
+def turbulence2d_run(n, t_end, precision="fp64", high_order=True, log_every=200,
+                     wall_limit=None, device="cuda", verbose=True):
+    """The 2D set-up of Sec. 5 on an n x n x 1 box (side 2 pi) up to t_end
+    (or until wall_limit seconds have passed): logs div B, the time per
+    simulation time unit, and the shell spectra of the perpendicular (x, y)
+    and parallel (z) components of v and B at the start and the end."""
+    prim5, bf, L = inputs.turbulence2d(n, device=device)
+    torch.cuda.empty_cache()
+    S = Solver(n, n, 1, L=L, precision=precision, high_order=high_order, collect_stats=False,
+               device=device)
+    S.init(prim5, bf)
+    del prim5, bf
+
+    def spectra(tag):
+        P = S.primitives()
+        t, st, _ = S.time()
+        out = {"tag": tag, "t": t, "step": st,
+               "E_v_perp": shell_spectrum([P[1], P[2]]).tolist(),
+               "E_v_par": shell_spectrum([P[3]]).tolist(),
+               "E_B_perp": shell_spectrum([P[5], P[6]]).tolist(),
+               "E_B_par": shell_spectrum([P[7]]).tolist()}
+        del P
+        return out
+
+    log = {"n": n, "precision": precision, "high_order": high_order, "spectra": [spectra("start")],
+           "divb": []}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    t, steps = 0.0, 0
+    while t < t_end:
+        S.step(log_every)
+        steps += log_every
+        t, _, dt = S.time()
+        d = S.diagnostics(raise_on_error=False)
+        wall = time.perf_counter() - t0
+        log["divb"].append((steps, t, d["divb_max"] * L[0] / n))
+        if verbose:
+            print(f"[run2d] {n}^2 {precision}{'+HO' if high_order else ''} step {steps} t={t:.3f} "
+                  f"dt={dt:.2e} wall={wall:.0f}s divB*dx={d['divb_max'] * L[0] / n:.1e} "
+                  f"rc={d['rc']}", flush=True)
+        if d["rc"] != 0:
+            log["error"] = d["rc"]
+            break
+        if wall_limit is not None and wall > wall_limit:
+            log["stopped_by_wall_limit"] = True
+            break
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    log.update({"t_final": t, "steps": steps, "seconds": wall,
+                "seconds_per_time_unit": wall / max(t, 1e-300),
+                "Mcell_updates_per_s": n * n * steps / wall / 1e6})
+    log["spectra"].append(spectra("end"))
+    end = log["spectra"][-1]
+    log["slopes_end"] = {key: {f"{a}-{b}": spectral_slope(end[key], a, b)
+                               for a, b in ((4, 32), (8, 128), (16, 512)) if b <= len(end[key])}
+                         for key in ("E_v_perp", "E_B_perp")}
+    S.close()
+    return log
+
+
 def spectral_slope(E, kmin=3, kmax=None):
     """Least-squares slope of log E against log k over [kmin, kmax]."""
     kmax = kmax or len(E)
@@ -137,9 +204,10 @@ def _summary(log):
 
 
 def main(argv=None):
-    """Long run of the turbulence set-up: plain FP64 first, then the mixed
+    """Long run of the 3D turbulence set-up: plain FP64 first, then the mixed
     form with the learned guess from the same initial state, and the
-    per-variable L1 difference of their final primitives."""
+    per-variable L1 difference of their final primitives.  With --2d: the
+    2D set-up of Sec. 5 up to --t-end in one form."""
     import argparse
     import json
     ap = argparse.ArgumentParser(description=main.__doc__)
@@ -148,7 +216,23 @@ def main(argv=None):
     ap.add_argument("--log-every", type=int, default=10)
     ap.add_argument("--spectrum-every", type=int, default=100)
     ap.add_argument("--out", default=None, help="write the JSON summary here")
+    ap.add_argument("--2d", dest="two_d", action="store_true")
+    ap.add_argument("--t-end", type=float, default=20.0)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--no-ho", action="store_true")
+    ap.add_argument("--wall-limit", type=float, default=None)
     args = ap.parse_args(argv)
+    if args.two_d:
+        log = turbulence2d_run(args.n, args.t_end, args.precision, not args.no_ho,
+                               log_every=args.log_every, wall_limit=args.wall_limit)
+        print("[run2d] done:", {k: log[k] for k in ("t_final", "steps", "seconds",
+                                                    "seconds_per_time_unit",
+                                                    "Mcell_updates_per_s", "slopes_end")},
+              flush=True)
+        if args.out:
+            with open(args.out, "w") as f:
+                json.dump(log, f)
+        return log
     from .learned import train_default
     mlp, hist, npairs = train_default()
     print(f"[run] learned guess trained on {npairs} pairs, loss {hist[-1][1]:.2e}", flush=True)

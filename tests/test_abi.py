@@ -40,7 +40,7 @@ def test_defaults_and_work_bytes(L):
 
 
 @pytest.mark.parametrize("field,value", [
-    ("nx", 4), ("nz", 7), ("gamma_ad", 1.0), ("gamma_ad", 2.5), ("cfl", 0.0), ("cfl", 1.5),
+    ("nx", 0), ("nz", -1), ("gamma_ad", 1.0), ("gamma_ad", 2.5), ("cfl", 0.0), ("cfl", 1.5),
     ("riemann", 5), ("precision", 7), ("guess", 9), ("newton_maxit", 0),
     ("newton_tol", 0.0), ("newton_tol", 0.5), ("pfloor", -1.0), ("lx", 0.0),
     ("dt_fixed", -1.0), ("recon", 2), ("time_order", 1), ("time_order", 4), ("high_order", 2),

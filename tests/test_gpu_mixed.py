@@ -107,9 +107,10 @@ def test_mixed_vs_oracle_64_and_vs_exact():
 
 
 def test_mixed_vs_fp64_gpu_512():
-    """512^3 diagonal CPA: mixed against the FP64 GPU path after 20 steps at
-    the same dt; conservation and div B at FP64 round-off in the mixed run."""
-    n, nsteps = 512, 20
+    """512^3 diagonal CPA (the mixed-precision configuration): mixed against
+    the FP64 GPU path after 200 steps at the same dt; conservation and div B
+    at FP64 round-off in the mixed run."""
+    n, nsteps = 512, 200
     dt = 0.5 / (3 * n)  # below both forms' CFL dt
     Pf, Bff, df = _run(n, nsteps, "fp64", dt, device_ic=True)
     Pm, Bfm, dm = _run(n, nsteps, "mixed", dt, device_ic=True)
@@ -120,8 +121,9 @@ def test_mixed_vs_fp64_gpu_512():
         errs.append(a / b)
     for k in range(3):
         errs.append((Bfm[k] - Bff[k]).abs().sum().item() / max(Bff[k].abs().sum().item(), Bff[k].numel()))
-    print("[gpu] mixed vs FP64 at 512^3, 20 steps (L1 rel):", ["%.2e" % e for e in errs], flush=True)
-    assert max(errs) < 1e-6
+    print("[gpu] mixed vs FP64 at 512^3, 200 steps (L1 rel):", ["%.2e" % e for e in errs],
+          flush=True)
+    assert max(errs) < 1e-5
     N = n ** 3
     assert dm["divb_max"] / n < 1e-12
     # totals of the mixed run match the FP64 run's to round-off (both conserve)

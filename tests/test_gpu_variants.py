@@ -180,3 +180,56 @@ def test_mixed_ho_close_to_fp64_ho():
         S.close()
     for q in range(8):
         assert l1rel(out["mixed"][q], out["fp64"][q], SCALE[q]) <= 1e-5, q
+
+
+@pytest.mark.parametrize("shape,kw,okw", [((2, 3, 20), dict(), dict()),
+                                          ((1, 5, 70), dict(high_order=True), dict(ho=1)),
+                                          ((3, 1, 9), dict(recon="mc"), dict(recon=1))])
+def test_rhs_thin_boxes(shape, kw, okw):
+    """Directions with fewer than 4 cells (stencils that wrap more than once)
+    on rough random states, against the oracle element by element."""
+    prim5, bf = _rough_state(shape, 31)
+    S = _solver(shape, **kw)
+    S.init(prim5, bf)
+    R, amax = S.rhs()
+    R = R.cpu().numpy()
+    S.close()
+    g = _oracle(shape, **okw)
+    cons, W = g.init(prim5, bf)
+    Pr, _, nf = g.c2p(cons, bf, W)
+    assert nf == 0
+    Rr, amax_r = g.rhs(Pr, bf)
+    assert amax.item() == pytest.approx(amax_r, rel=1e-13)
+    for q in range(8):
+        scale = max(np.abs(Rr[q]).max(), 1e-300)
+        np.testing.assert_allclose(R[q], Rr[q], rtol=0, atol=1e-9 * scale, err_msg=f"comp {q}")
+
+
+@pytest.mark.parametrize("kw,okw", [(dict(high_order=True), dict(ho=1)), (dict(), dict())])
+def test_2d_turbulence_step_parity(kw, okw):
+    """The 2D set-up of Sec. 5 on a 48 x 48 x 1 box, 5 steps: primitives and
+    face B within L1 1e-12 of the oracle (velocity scale v_A/4, field scale
+    B0/4 for the fluctuating components)."""
+    n = 48
+    prim5, bf, L = I.turbulence2d(n)
+    shape = (1, n, n)
+    S = _solver(shape, L=L, **kw)
+    S.init(prim5, bf)
+    S.step(5)
+    P = S.primitives().cpu().numpy()
+    d = S.diagnostics()
+    Bg = S.bface.cpu().numpy()
+    S.close()
+    g = O.Grid(n, n, 1, lx=L[0], ly=L[1], lz=L[2], **okw)
+    cons, W = g.init(prim5, bf)
+    bfo = [b.copy() for b in bf]
+    _, _, nf = g.step(cons, bfo, W, 5)
+    Pr, _, _ = g.c2p(cons, bfo, W)
+    assert nf == 0 and d["c2p_failures"] == 0
+    va = 10.0 / np.sqrt(301.0)
+    sc = [1.0, va / 4, va / 4, va / 4, 50.0, 2.5, 2.5, 10.0]
+    for q in range(8):
+        assert l1rel(P[q], Pr[q], sc[q]) <= 1e-12, q
+    for k in range(3):
+        assert l1rel(Bg[k], bfo[k], sc[5 + k]) <= 1e-12
+    assert d["divb_max"] * L[0] / n < 1e-11

@@ -284,3 +284,42 @@ def test_rk2_conserves_and_preserves_uniform_state():
     s1 = g.sums(cons, bf)
     for a, b in zip(s0, s1):
         assert abs(a - b) <= 1e-12 * max(1.0, abs(b))
+
+
+@pytest.mark.parametrize("kw", [dict(), dict(ho=1)])
+def test_z_uniform_box_equals_replicated(kw):
+    """A box one cell deep in z (the 2D set-up of Sec. 5) gives, bitwise, the
+    operator of the same z-uniform data on a box four cells deep: the
+    stencils wrap onto the single layer exactly as onto identical layers."""
+    prim5, bf, L = I.turbulence2d(24)
+    g1 = O.Grid(24, 24, 1, lx=L[0], ly=L[1], lz=L[2], **kw)
+    cons, W = g1.init(prim5, bf)
+    P1, _, nf = g1.c2p(cons, bf, W)
+    assert nf == 0
+    R1, a1 = g1.rhs(P1, bf)
+    rep = lambda a: np.ascontiguousarray(np.repeat(a, 4, axis=0))
+    g4 = O.Grid(24, 24, 4, lx=L[0], ly=L[1], lz=4 * L[2], **kw)
+    cons4, W4 = g4.init([rep(a) for a in prim5], [rep(b) for b in bf])
+    P4, _, _ = g4.c2p(cons4, [rep(b) for b in bf], W4)
+    R4, a4 = g4.rhs(P4, [rep(b) for b in bf])
+    assert a1 == a4
+    for q in range(8):
+        for k in range(4):
+            assert np.array_equal(R4[q][k], R1[q][0]), (q, k)
+
+
+def test_turbulence2d_initial_data():
+    """Sec. 5 set-up: B0 = 10, p0 = 50, v_A = 10/sqrt(301) ~ 0.576 (the
+    paper prints 0.57), <|dv|>/v_A = <|dB|>/B0 = 0.25, div B = 0 to
+    round-off, 24 modes with 1 <= |k| <= 4."""
+    n = 32
+    prim5, bf, L = I.turbulence2d(n)
+    va = 10.0 / math.sqrt(301.0)
+    assert va == pytest.approx(0.57, abs=0.01)
+    assert np.all(prim5[0] == 1.0) and np.all(prim5[4] == 50.0) and np.all(bf[2] == 10.0)
+    assert np.mean(np.hypot(prim5[1], prim5[2])) / va == pytest.approx(0.25, rel=1e-12)
+    h = L[0] / n
+    div = (bf[0] - np.roll(bf[0], 1, axis=2)) / h + (bf[1] - np.roll(bf[1], 1, axis=1)) / h
+    assert np.abs(div).max() < 1e-12
+    modes = I.turbulence2d_modes()
+    assert len(modes) == 24 and all(1 <= math.hypot(*k) <= 4 for k in modes)
