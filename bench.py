@@ -123,6 +123,9 @@ def run_form(n, precision, steps, warmup, mlp=None, **scheme):
     e1.record(S.stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
+    S.kernel_timing(True)
+    S.step(2)
+    kt = S.kernel_times()
     S.close()
     # Newton statistics of the same form (a separate run with counters on)
     prim5, bf, _ = inputs.cpa(n, diagonal=True, device="cuda")
@@ -143,7 +146,8 @@ def run_form(n, precision, steps, warmup, mlp=None, **scheme):
             "Mcell_updates_per_s": round(v, 1),
             "hbm_roofline_frac_step": round(v * 1e6 * sb / (HBM_PEAK_GBS * 1e9), 4),
             "newton_mean_iters": round(d["newton_iters"] / max(d["newton_calls"], 1), 3),
-            "mlp_fallback_rate": round(d["mlp_fallbacks"] / max(d["newton_calls"], 1), 5)}
+            "mlp_fallback_rate": round(d["mlp_fallbacks"] / max(d["newton_calls"], 1), 5),
+            "kernel_ms": {k: round(t / c, 4) for k, (t, c) in kt.items() if c}}
 
 
 def cpu_baseline(seconds_target=15.0):

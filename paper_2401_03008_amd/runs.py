@@ -131,7 +131,7 @@ def turbulence2d_run(n, t_end, precision="fp64", high_order=True, log_every=200,
         return out
 
     log = {"n": n, "precision": precision, "high_order": high_order, "spectra": [spectra("start")],
-           "divb": []}
+           "divb": [], "divb0": S.diagnostics()["divb_max"] * L[0] / n}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     t, steps = 0.0, 0
