@@ -78,13 +78,19 @@ __device__ __forceinline__ int lane_id() { return threadIdx.x; }
 // Stencil indices along direction dir at offsets first..first+5 (periodic,
 // first >= -3).  A direction with fewer than 4 cells (a 2D or 1D box: the
 // stencil wraps more than once) takes the general modulo.
-__device__ __forceinline__ void stencil6_from(const GridDims& g, const Cell& c, int dir,
-                                              int first, int* idx) {
+// THIN selects the modulo form at compile time (for kernels whose body is
+// instantiated for both cases); the untemplated form branches on n.
+template <bool THIN>
+__device__ __forceinline__ void stencil6_t(const GridDims& g, const Cell& c, int dir, int first,
+                                           int* idx) {
   const int n = dir == 0 ? g.nx : (dir == 1 ? g.ny : g.nz);
   const int co = dir == 0 ? c.i : (dir == 1 ? c.j : c.k);
   const int stride = dir == 0 ? 1 : (dir == 1 ? g.nx : g.nx * g.ny);
   const int base = c.id - co * stride;
-  if (n >= 4) {
+  if (THIN) {
+#pragma unroll
+    for (int m = 0; m < 6; ++m) idx[m] = base + ((co + m + first + 3 * n) % n) * stride;
+  } else {
 #pragma unroll
     for (int m = 0; m < 6; ++m) {
       int cm = co + m + first;
@@ -92,10 +98,18 @@ __device__ __forceinline__ void stencil6_from(const GridDims& g, const Cell& c, 
       cm -= cm >= n ? n : 0;
       idx[m] = base + cm * stride;
     }
-  } else {
-#pragma unroll
-    for (int m = 0; m < 6; ++m) idx[m] = base + ((co + m + first + 3 * n) % n) * stride;
   }
+}
+
+__device__ __forceinline__ bool thin_box(const GridDims& g) {
+  return g.nx < 4 || g.ny < 4 || g.nz < 4;
+}
+
+__device__ __forceinline__ void stencil6_from(const GridDims& g, const Cell& c, int dir,
+                                              int first, int* idx) {
+  const int n = dir == 0 ? g.nx : (dir == 1 ? g.ny : g.nz);
+  if (n >= 4) stencil6_t<false>(g, c, dir, first, idx);
+  else stencil6_t<true>(g, c, dir, first, idx);
 }
 
 // REC stencil of the +face along dir: cells at offsets -2..+3.
@@ -691,10 +705,8 @@ template void launch_uct3<float>(const Uct3Args<float>&, int, hipStream_t);
 // SSP-RK2: stage 1, then stage 4: U^{n+1} = 1/2 U^n + 1/2 (U1 + dt L(U1)).
 // Stage 0 writes L only.  Stage 1 writes U1 to a work register, so U^n stays
 // in the caller's arrays and is read back by the later stages (no copy).
-template <int STAGE, typename TS, bool HO>
-__global__ __launch_bounds__(kThreads) void k_update(UpdArgs<TS> a) {
-  const Cell c = cell_of(a.g);
-  if (!c.valid) return;
+template <int STAGE, typename TS, bool HO, bool THIN>
+__device__ __forceinline__ void update_cell(const UpdArgs<TS>& a, const Cell& c) {
   const double* ix = a.g.inv_dx;
   const double* Ex = a.e[0];
   const double* Ey = a.e[1];
@@ -703,7 +715,7 @@ __global__ __launch_bounds__(kThreads) void k_update(UpdArgs<TS> a) {
   if (HO) {
     int s[3][6];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) stencil6_from(a.g, c, d, -3, s[d]);
+    for (int d = 0; d < 3; ++d) stencil6_t<THIN>(a.g, c, d, -3, s[d]);
 #pragma unroll
     for (int n = 0; n < 5; ++n) {
       double acc = 0.0;
@@ -749,6 +761,16 @@ __global__ __launch_bounds__(kThreads) void k_update(UpdArgs<TS> a) {
       a.uout[n][c.id] = 0.5 * a.u0[n][c.id] + 0.5 * (u + dt * r[n]);
     }
   }
+}
+
+// The HO body is instantiated separately for thin boxes, so that the common
+// case keeps its own schedule (all stencil loads in flight together).
+template <int STAGE, typename TS, bool HO>
+__global__ __launch_bounds__(kThreads) void k_update(UpdArgs<TS> a) {
+  const Cell c = cell_of(a.g);
+  if (!c.valid) return;
+  if (HO && thin_box(a.g)) update_cell<STAGE, TS, HO, true>(a, c);
+  else update_cell<STAGE, TS, HO, false>(a, c);
 }
 
 template <typename TS, bool HO>

@@ -86,6 +86,12 @@ def turbulence_run(n, steps, precision="fp64", mlp=None, sigma0=10.0, gamma_max=
             break
     torch.cuda.synchronize()
     log["seconds"] = time.perf_counter() - t0
+    if "error" not in log:
+        P = S.primitives()
+        t, _, _ = S.time()
+        log["spectra"].append({"step": done, "t": t, "E_v": shell_spectrum([P[1], P[2], P[3]]).tolist(),
+                               "E_B": shell_spectrum([P[5], P[6], P[7]]).tolist()})
+        del P
     d = S.diagnostics(raise_on_error=False)
     h = d["newton_hist"]
     tot = max(sum(h), 1)

@@ -236,7 +236,7 @@ def test_turbulence_run_driver_small():
     b = turbulence_run(64, 20, precision="mixed", mlp=mlp, log_every=10, spectrum_every=10)
     assert "error" not in a and "error" not in b
     assert max(x[2] for x in a["divb"]) < 1e-11 and max(x[2] for x in b["divb"]) < 1e-11
-    assert len(a["spectra"]) == 2 and len(a["spectra"][0]["E_v"]) == 31
+    assert len(a["spectra"]) == 3 and len(a["spectra"][0]["E_v"]) == 31  # steps 0, 10, 20
     diff = compare_runs(b, a)
     print("[gpu] mixed+learned vs fp64 (64^3 turbulence, 20 steps):", ["%.1e" % d for d in diff],
           "newton", a["newton"], b["newton"], flush=True)
