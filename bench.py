@@ -13,7 +13,12 @@ Prints one JSON line.  Besides the contract keys it carries:
                    duration from HIP events recorded on the library's stream
                    during a second, instrumented run of the same steps;
   cpu_baseline  -- the FP64 CPU oracle timed on this host on a bounded sample
-                   (the same wave at 64^3, a few steps, all cores).
+                   (the same wave at 64^3, a few steps, all cores; then one
+                   thread);
+  forms         -- the same wave at 512^3 in the FP64 and mixed forms, each
+                   also with HO, with MC + SSP-RK2 and with the learned Newton
+                   guess (rate, step-level HBM fraction, per-kernel ms), and
+                   the learned guess's iteration report on 512^3 turbulence.
 """
 import argparse
 import json

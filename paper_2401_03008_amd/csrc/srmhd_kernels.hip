@@ -101,10 +101,6 @@ __device__ __forceinline__ void stencil6_t(const GridDims& g, const Cell& c, int
   }
 }
 
-__device__ __forceinline__ bool thin_box(const GridDims& g) {
-  return g.nx < 4 || g.ny < 4 || g.nz < 4;
-}
-
 __device__ __forceinline__ void stencil6_from(const GridDims& g, const Cell& c, int dir,
                                               int first, int* idx) {
   const int n = dir == 0 ? g.nx : (dir == 1 ? g.ny : g.nz);
@@ -763,33 +759,35 @@ __device__ __forceinline__ void update_cell(const UpdArgs<TS>& a, const Cell& c)
   }
 }
 
-// The HO body is instantiated separately for thin boxes, so that the common
-// case keeps its own schedule (all stencil loads in flight together).
-template <int STAGE, typename TS, bool HO>
+// The HO form has its own kernel for thin boxes (chosen on the host), so the
+// common case keeps a schedule with all stencil loads in flight together (a
+// run-time branch between the two index forms serialised them).
+template <int STAGE, typename TS, bool HO, bool THIN>
 __global__ __launch_bounds__(kThreads) void k_update(UpdArgs<TS> a) {
   const Cell c = cell_of(a.g);
   if (!c.valid) return;
-  if (HO && thin_box(a.g)) update_cell<STAGE, TS, HO, true>(a, c);
-  else update_cell<STAGE, TS, HO, false>(a, c);
+  update_cell<STAGE, TS, HO, THIN>(a, c);
 }
 
-template <typename TS, bool HO>
+template <typename TS, bool HO, bool THIN>
 void launch_update_ho(int stage, const UpdArgs<TS>& a, hipStream_t s) {
   const dim3 grid = cell_grid(a.g);
   dim3 blk(kBlockX, kBlockY);
   switch (stage) {
-    case 0: hipLaunchKernelGGL((k_update<0, TS, HO>), grid, blk, 0, s, a); break;
-    case 1: hipLaunchKernelGGL((k_update<1, TS, HO>), grid, blk, 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_update<2, TS, HO>), grid, blk, 0, s, a); break;
-    case 3: hipLaunchKernelGGL((k_update<3, TS, HO>), grid, blk, 0, s, a); break;
-    default: hipLaunchKernelGGL((k_update<4, TS, HO>), grid, blk, 0, s, a); break;
+    case 0: hipLaunchKernelGGL((k_update<0, TS, HO, THIN>), grid, blk, 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_update<1, TS, HO, THIN>), grid, blk, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_update<2, TS, HO, THIN>), grid, blk, 0, s, a); break;
+    case 3: hipLaunchKernelGGL((k_update<3, TS, HO, THIN>), grid, blk, 0, s, a); break;
+    default: hipLaunchKernelGGL((k_update<4, TS, HO, THIN>), grid, blk, 0, s, a); break;
   }
 }
 
 template <typename TS>
 void launch_update(int stage, const UpdArgs<TS>& a, bool ho, hipStream_t s) {
-  if (ho) launch_update_ho<TS, true>(stage, a, s);
-  else launch_update_ho<TS, false>(stage, a, s);
+  const bool thin = a.g.nx < 4 || a.g.ny < 4 || a.g.nz < 4;
+  if (!ho) launch_update_ho<TS, false, false>(stage, a, s);
+  else if (thin) launch_update_ho<TS, true, true>(stage, a, s);
+  else launch_update_ho<TS, true, false>(stage, a, s);
 }
 template void launch_update<double>(int, const UpdArgs<double>&, bool, hipStream_t);
 template void launch_update<float>(int, const UpdArgs<float>&, bool, hipStream_t);
