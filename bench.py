@@ -223,7 +223,7 @@ def newton_report_turbulence(n, mlp, steps=4):
                "p50": next(i for i, c in enumerate(cdf) if c >= 0.5),
                "p99": next(i for i, c in enumerate(cdf) if c >= 0.99),
                "fallback_rate": round(d["mlp_fallbacks"] / max(d["newton_calls"], 1), 5),
-               "c2p_ms": round(kt["c2p"][0] / max(kt["c2p"][1], 1), 4),
+               "c2p_ms": round((kt["c2p"][0] + kt["mlp_guess"][0]) / max(kt["c2p"][1], 1), 4),
                "c2p_failures": d["c2p_failures"], "rc": d["rc"]}
         P = S.primitives()
         if guess == "prev":
