@@ -63,11 +63,12 @@ KERNEL_UNITS = {
 # launches per step), for the HBM traffic read from the profiles
 PROFILED_KERNEL = {
     "c2p": [("k_c2p<false, false>", 3)],
-    "flux_x": [("k_flux<0, double, false, false>", 3)],
-    "flux_y": [("k_flux<1, double, false, false>", 3)],
-    "flux_z": [("k_flux<2, double, true, false>", 1), ("k_flux<2, double, false, false>", 2)],
-    "uct": [("k_uct3<double>", 3)],
-    "update": [("k_update<1, double>", 1), ("k_update<2, double>", 1), ("k_update<3, double>", 1)],
+    "flux_x": [("k_flux<0, double, false, false, 0>", 3)],
+    "flux_y": [("k_flux<1, double, false, false, 0>", 3)],
+    "flux_z": [("k_flux<2, double, true, false, 0>", 1), ("k_flux<2, double, false, false, 0>", 2)],
+    "uct": [("k_uct3<double, 0>", 3)],
+    "update": [("k_update<1, double, false, false>", 1), ("k_update<2, double, false, false>", 1),
+               ("k_update<3, double, false, false>", 1)],
 }
 
 
@@ -223,7 +224,7 @@ def newton_report_turbulence(n, mlp, steps=4):
                "p50": next(i for i, c in enumerate(cdf) if c >= 0.5),
                "p99": next(i for i, c in enumerate(cdf) if c >= 0.99),
                "fallback_rate": round(d["mlp_fallbacks"] / max(d["newton_calls"], 1), 5),
-               "c2p_ms": round((kt["c2p"][0] + kt["mlp_guess"][0]) / max(kt["c2p"][1], 1), 4),
+               "c2p_ms": round(kt["c2p"][0] / max(kt["c2p"][1], 1), 4),
                "c2p_failures": d["c2p_failures"], "rc": d["rc"]}
         P = S.primitives()
         if guess == "prev":

@@ -33,7 +33,6 @@ struct srmhd_ctx {
   void* fhat[3][5];
   void* apm[3][2];
   void* fv[3][4];
-  float* w0;  // learned guess W0 (FP32)
   double* edge[3];
   std::string err;
   // per-kernel event timing
@@ -147,7 +146,7 @@ Layout layout_of(const srmhd_config* c) {
   // RK register (8) + edge E (3) always FP64; prims FP64 (8) or FP32 (8); faces
   // (15 fluxes + 6 speeds + 12 velocity states) in the flux precision.
   L.n64 = 8 + 3 + (mixed ? 0 : 8 + 33);
-  L.n32 = (mixed ? 8 + 33 : 0) + 1;  // + the learned guess W0 (FP32)
+  L.n32 = mixed ? 8 + 33 : 0;
   L.total = L.off_arr + L.n64 * L.arr_bytes64 + L.n32 * L.arr_bytes32;
   return L;
 }
@@ -252,13 +251,8 @@ void launch_c2p_into(srmhd_ctx* c, const StageState& st, double* const* prim64,
   a.guess = guess;
   a.ho = c->cfg.high_order;
   a.mlp = c->mlp;
-  a.w0 = c->w0;
   a.counters = c->counters;
   a.err = &c->sc->err;
-  if (guess == 1) {
-    KTimer kt(c, 5);
-    launch_mlp_guess(a, c->stream);
-  }
   KTimer kt(c, 0);
   launch_c2p(a, c->cfg.collect_stats != 0, c->stream);
 }
@@ -389,7 +383,6 @@ int srmhd_create(const srmhd_config* cfg, const srmhd_buffers* buf, void* stream
     for (int n = 0; n < 2; ++n) c->apm[d][n] = takeT();
     for (int n = 0; n < 4; ++n) c->fv[d][n] = takeT();
   }
-  c->w0 = take32();
   // clear scalars and counters (a fill kernel, no memset node)
   launch_zero_u64((unsigned long long*)w, L.off_part / sizeof(unsigned long long), c->stream);
   const int rc = check_launch(c, "clearing work scalars");

@@ -335,47 +335,15 @@ __device__ int con2prim(const double* u, double bx, double by, double bz, double
   return 0;
 }
 
-// Learned guess, its own pass (so that the network's registers do not limit
-// the occupancy of the inversion): the network's (log(p/D), log Gamma) of
-// each cell's conserved state gives W0 = D Gamma + g/(g-1) p Gamma^2, stored
-// in FP32 (-1 when the features are not finite).  Every lane of a wavefront
-// takes part in the matrix-core products, valid or not.
-__global__ __launch_bounds__(kThreads) void k_mlp_guess(C2PArgs a) {
-  __shared__ __align__(16) uint16_t s_lx[kBlockY * 64 * 16];
-  __shared__ float s_ly[kBlockY * 128];
-  const Cell c = cell_of(a.g);
-  double u[5] = {1.0, 0.0, 0.0, 0.0, 1.0};
-  double b[3] = {0.0, 0.0, 0.0};
-  if (c.valid) {
-    for (int n = 0; n < 5; ++n) u[n] = a.cons[n][c.id];
-    for (int d = 0; d < 3; ++d) b[d] = centre_b(a.g, c, a.bf[d], d, a.ho);
-  }
-  const double S2 = u[1] * u[1] + u[2] * u[2] + u[3] * u[3];
-  const double B2 = b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
-  const double tau = u[1] * b[0] + u[2] * b[1] + u[3] * b[2];
-  float fe[kMlpIn];
-  mlp_features_f32(u[0], S2, B2, tau, u[4], fe);
-  bool fin = true;
-  for (int k = 0; k < kMlpIn; ++k) fin = fin && isfinite(fe[k]);
-  if (!fin)
-    for (int k = 0; k < kMlpIn; ++k) fe[k] = 0.f;
-  float out[kMlpOut];
-  mlp_wave(a.mlp, fe, &s_lx[threadIdx.y * 64 * 16], &s_ly[threadIdx.y * 128], out,
-           []() { __syncthreads(); });
-  if (c.valid) {
-    const double lor = (double)__expf(fmaxf(out[1], 0.f));
-    const double pg = u[0] * (double)__expf(out[0]);
-    a.w0[c.id] = fin ? (float)(u[0] * lor + a.gam / (a.gam - 1.0) * pg * lor * lor) : -1.f;
-  }
-}
-
 // Guess: the previous W (mode 0), a cold start from U (mode 2), or the
-// learned W0 of k_mlp_guess (mode 1): if Newton from W0 does not converge,
-// or W0 is unusable, the inversion is redone from the previous W and
-// counted.
+// learned guess (mode 1): the network's (log(p/D), log Gamma) gives
+// W0 = D Gamma + g/(g-1) p Gamma^2; if Newton from W0 does not converge, or W0
+// is unusable, the inversion is redone from the previous W and counted.
 template <bool STATS, bool MLP>
 __global__ __launch_bounds__(kThreads) void k_c2p(C2PArgs a) {
   __shared__ unsigned s_cnt[CNT_N];
+  __shared__ __align__(16) uint16_t s_lx[MLP ? kBlockY * 64 * 16 : 4];
+  __shared__ float s_ly[MLP ? kBlockY * 128 : 1];
   BlockCounters bc;
   if (STATS) bc.init(s_cnt);
   const Cell c = cell_of(a.g);
@@ -392,8 +360,22 @@ __global__ __launch_bounds__(kThreads) void k_c2p(C2PArgs a) {
   double pr[5];
   double W = Wprev;
   if (MLP) {
+    const double S2 = u[1] * u[1] + u[2] * u[2] + u[3] * u[3];
+    const double B2 = b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
+    const double tau = u[1] * b[0] + u[2] * b[1] + u[3] * b[2];
+    float fe[kMlpIn];
+    mlp_features_f32(u[0], S2, B2, tau, u[4], fe);
+    bool fin = true;
+    for (int k = 0; k < kMlpIn; ++k) fin = fin && isfinite(fe[k]);
+    if (!fin)
+      for (int k = 0; k < kMlpIn; ++k) fe[k] = 0.f;
+    float out[kMlpOut];
+    mlp_wave(a.mlp, fe, &s_lx[threadIdx.y * 64 * 16], &s_ly[threadIdx.y * 128], out,
+             []() { __syncthreads(); });
+    const double lor = (double)__expf(fmaxf(out[1], 0.f));
+    const double pg = u[0] * (double)__expf(out[0]);
+    W = fin ? u[0] * lor + a.gam / (a.gam - 1.0) * pg * lor * lor : -1.0;
     if (c.valid) {
-      W = (double)a.w0[c.id];
       rc = con2prim(u, b[0], b[1], b[2], a.gam, W, a.maxit, a.tol, a.pfloor, pr, iters, floored,
                     true);
       if (rc == 1 || rc == 4) {
@@ -431,10 +413,6 @@ __global__ __launch_bounds__(kThreads) void k_c2p(C2PArgs a) {
     bc.add_hist(CNT_HIST0, c.valid, iters < 31 ? iters : 31);
     bc.flush(a.counters);
   }
-}
-
-void launch_mlp_guess(const C2PArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_mlp_guess, cell_grid(a.g), dim3(kBlockX, kBlockY), 0, s, a);
 }
 
 void launch_c2p(const C2PArgs& a, bool stats, hipStream_t s) {

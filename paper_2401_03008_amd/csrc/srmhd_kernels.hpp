@@ -61,7 +61,6 @@ struct C2PArgs {
   int guess;  // 0 = previous W, 1 = learned guess (fallback previous W), 2 = cold start
   int ho;     // 1: sixth-order INT of the face B
   MlpDev mlp;
-  float* w0;  // learned guess W0 per cell (written by k_mlp_guess, read in mode 1)
   unsigned long long* counters;
   unsigned int* err;
 };
@@ -147,7 +146,6 @@ struct ReduceArgs {
 // Launchers (srmhd_kernels.hip).  All asynchronous on `stream`.
 void launch_init(const InitArgs& a, hipStream_t s);
 void launch_c2p(const C2PArgs& a, bool stats, hipStream_t s);
-void launch_mlp_guess(const C2PArgs& a, hipStream_t s);
 void launch_harvest(const HarvestArgs& a, hipStream_t s);
 // rec: kRecMp5, kRecMc or kRecMp5Point (srmhd_phys.hpp).  Update stages: 0 =
 // L(U) only, 1..3 = SSP-RK3 stages, 4 = second (last) SSP-RK2 stage; ho:

@@ -215,7 +215,7 @@ def test_iteration_report_turbulence():
         rows[guess] = {"mean_iters": d["newton_iters"] / d["newton_calls"],
                        "p50": int(np.searchsorted(cdf, 0.5)), "p99": int(np.searchsorted(cdf, 0.99)),
                        "fallback_rate": d["mlp_fallbacks"] / d["newton_calls"],
-                       "c2p_ms": (kt["c2p"][0] + kt["mlp_guess"][0]) / max(kt["c2p"][1], 1),
+                       "c2p_ms": kt["c2p"][0] / max(kt["c2p"][1], 1),
                        "failures": d["c2p_failures"]}
     print("[gpu] Newton iterations (turbulence 128^3, 4 steps):", rows, flush=True)
     for g in rows:
