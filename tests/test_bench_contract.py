@@ -1,0 +1,26 @@
+"""Host-side parts of the benchmark contract (no GPU needed)."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_kernel_units_and_profile_lookup():
+    """Every timed kernel class has algorithmic bytes/flops, and the traffic
+    lookup names kernels the profile summary lists (or returns None when the
+    kernel sources changed since it was taken)."""
+    sys.path.insert(0, ROOT)
+    import bench
+    assert set(bench.PROFILED_KERNEL) == set(bench.KERNEL_UNITS)
+    for cls, (b64, bmx, fl) in bench.KERNEL_UNITS.items():
+        assert b64 > bmx > 0 and fl > 0
+        t = bench.profiled_traffic(cls)
+        assert t is None or t > 0.5 * b64 * 256 ** 3

@@ -223,6 +223,10 @@ def test_iteration_report_turbulence():
     a = (prims["mlp"] - prims["prev"]).abs().sum().item() / prims["prev"].abs().sum().item()
     assert a < 1e-10
     assert rows["cold"]["mean_iters"] > rows["prev"]["mean_iters"]
+    # what the trained network gains: fewer iterations than a start from U
+    # (the only guess available without a previous W), by at least a quarter
+    assert rows["mlp"]["mean_iters"] < 0.75 * rows["cold"]["mean_iters"]
+    assert rows["mlp"]["fallback_rate"] < 0.01
 
 
 def test_turbulence_run_driver_small():

@@ -80,7 +80,7 @@ def test_cpa_state_closed_form(diagonal):
         assert S @ XYZ[0] == pytest.approx(va, rel=1e-14)
         Sperp = S - (S @ XYZ[0]) * XYZ[0]
         np.testing.assert_allclose(Sperp, va * (1.0 - (W + 2.0)) * Bperp, rtol=1e-14, atol=1e-15)
-    # survey's numeric values of the same closed forms
+    # the same closed forms evaluated: W = rho h Gamma^2 = 5 / (1 - v_A^2)
     assert W == pytest.approx(5.8541019662, rel=1e-10)
     assert W - 1.0 + 0.5 * (va * va + 2.0) == pytest.approx(5.9270509831, rel=1e-10)
 
@@ -175,7 +175,8 @@ def _random_prims(rng):
 
 @pytest.mark.parametrize("guess", ["exact", "perturbed", "cold"])
 def test_con2prim_round_trip(guess):
-    """prim -> cons -> prim over the survey's sampling box.  Bounds:
+    """prim -> cons -> prim over rho in [1e-2, 1e2], p/rho in [1e-3, 1e2],
+    Gamma <= 10, sigma <= 100.  Bounds:
     rho and v relative 1e-11, p relative 1e-12 max(1, (B^2 + W)/p) (p is a
     small difference of large terms at high magnetisation and low p)."""
     rng = np.random.default_rng(1234)
