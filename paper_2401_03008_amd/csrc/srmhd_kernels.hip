@@ -482,22 +482,22 @@ void launch_harvest(const HarvestArgs& a, hipStream_t s) {
 // states of v_DIR and v_{DIR+1}, the two velocity components that the edge
 // field E_{DIR+2} needs at these faces.  With CFL, also the workgroup max of sum_d max(a+,a-)_d/dx_d
 // (needs the other two directions' speeds already stored).
-// Tile per direction: 64x4x1 for x and y, 64x1x4 for z (the four wavefronts
-// of a z tile share 9 of their 24 stencil planes).  Measured at 256^3: the z
-// tile takes 3% off the z pass; taller tiles (64x16x1 for y, 64x1x16 for z)
-// were 10-14% slower.
-template <int DIR>
-struct FluxTile : Tile<DIR == 2 ? 1 : 4, DIR == 2 ? 4 : 1> {};
+// Tile per direction: 64x4x1 for x and y; for z 64x1x4 in FP64 and 64x1x8
+// in FP32 (the wavefronts of a z tile share stencil planes).  Measured at
+// 256^3: the FP64 z tile takes 3% off the z pass, the FP32 one 20%; taller
+// FP64 tiles (64x16x1 for y, 64x1x8 or 64x1x16 for z) were slower.
+template <int DIR, typename TS>
+struct FluxTile : Tile<DIR == 2 ? 1 : 4, DIR == 2 ? (sizeof(TS) == 4 ? 8 : 4) : 1> {};
 
 template <int DIR, typename TS, bool CFL, bool STATS, int REC>
-__global__ __launch_bounds__(FluxTile<DIR>::kThreads) void k_flux(FluxArgs<TS> a) {
+__global__ __launch_bounds__((FluxTile<DIR, TS>::kThreads)) void k_flux(FluxArgs<TS> a) {
   using T = TS;
   constexpr int T1 = (DIR + 1) % 3, T2 = (DIR + 2) % 3;
   __shared__ unsigned s_cnt[CNT_N];
   __shared__ double s_max[16];
   BlockCounters bc;
   if (STATS) bc.init(s_cnt);
-  const Cell c = cell_of_tile<FluxTile<DIR>::kY, FluxTile<DIR>::kZ>(a.g);
+  const Cell c = cell_of_tile<FluxTile<DIR, TS>::kY, FluxTile<DIR, TS>::kZ>(a.g);
   int nfb = 0;
   double cfl_sum = 0.0;
   if (c.valid) {
@@ -595,8 +595,8 @@ template <typename TS, int REC>
 void launch_flux_rec(int dir, const FluxArgs<TS>& a, bool cfl, bool stats, hipStream_t s) {
 #define SRMHD_FLUX(D, C, S)                                                               \
   hipLaunchKernelGGL((k_flux<D, TS, C, S, REC>),                                          \
-                     (tile_grid<FluxTile<D>::kY, FluxTile<D>::kZ>(a.g)),                  \
-                     (tile_block<FluxTile<D>::kY, FluxTile<D>::kZ>()), 0, s, a)
+                     (tile_grid<FluxTile<D, TS>::kY, FluxTile<D, TS>::kZ>(a.g)),          \
+                     (tile_block<FluxTile<D, TS>::kY, FluxTile<D, TS>::kZ>()), 0, s, a)
   if (dir == 0) {
     if (stats) SRMHD_FLUX(0, false, true); else SRMHD_FLUX(0, false, false);
   } else if (dir == 1) {
@@ -668,13 +668,15 @@ __device__ __forceinline__ double uct_one(const Uct3Args<TS>& a, int id, const i
                           bpL, bpR);
 }
 
-// The edge stencils run along all three directions; 64x4x1 tiles measured as
-// fast as 64x2x2 and faster than 64x4x4.
-using UctTile = Tile<4, 1>;
+// The edge stencils run along all three directions.  FP64: 64x1x4 tiles
+// (1.3% faster than 64x4x1 at 256^3); FP32: 64x4x1 (64x2x2 and 64x1x4 the
+// same); 64x4x4 was slower.
+template <typename TS>
+using UctTile = Tile<sizeof(TS) == 8 ? 1 : 4, sizeof(TS) == 8 ? 4 : 1>;
 
 template <typename TS, int REC>
-__global__ __launch_bounds__(UctTile::kThreads) void k_uct3(Uct3Args<TS> a) {
-  const Cell c = cell_of_tile<UctTile::kY, UctTile::kZ>(a.g);
+__global__ __launch_bounds__(UctTile<TS>::kThreads) void k_uct3(Uct3Args<TS> a) {
+  const Cell c = cell_of_tile<UctTile<TS>::kY, UctTile<TS>::kZ>(a.g);
   if (!c.valid) return;
   int sx[6], sy[6], sz[6];
   stencil6(a.g, c, 0, sx);
@@ -688,8 +690,8 @@ __global__ __launch_bounds__(UctTile::kThreads) void k_uct3(Uct3Args<TS> a) {
 
 template <typename TS>
 void launch_uct3(const Uct3Args<TS>& a, int rec, hipStream_t s) {
-  const dim3 grid = tile_grid<UctTile::kY, UctTile::kZ>(a.g);
-  const dim3 blk = tile_block<UctTile::kY, UctTile::kZ>();
+  const dim3 grid = tile_grid<UctTile<TS>::kY, UctTile<TS>::kZ>(a.g);
+  const dim3 blk = tile_block<UctTile<TS>::kY, UctTile<TS>::kZ>();
   if (rec == kRecMc) hipLaunchKernelGGL((k_uct3<TS, kRecMc>), grid, blk, 0, s, a);
   else if (rec == kRecMp5Point) hipLaunchKernelGGL((k_uct3<TS, kRecMp5Point>), grid, blk, 0, s, a);
   else hipLaunchKernelGGL((k_uct3<TS, kRecMp5>), grid, blk, 0, s, a);
