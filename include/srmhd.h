@@ -1,6 +1,7 @@
 /*
- * srmhd.h -- C ABI of libsrmhd.so: one SSP-RK3 step of 3D ideal special-
- * relativistic MHD (flat space, Cartesian, periodic box) on an MI355X.
+ * srmhd.h -- C ABI of libsrmhd.so: SSP Runge-Kutta steps of 3D ideal special-
+ * relativistic MHD (flat space, Cartesian, periodic box) on an MI355X, with a
+ * learned Newton guess and its training kernels.
  *
  * The method follows Del Zanna et al., "A GPU-Accelerated Modern Fortran
  * Version of the ECHO Code for Relativistic Magnetohydrodynamics" (arXiv

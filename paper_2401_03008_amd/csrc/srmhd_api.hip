@@ -1,6 +1,6 @@
 // srmhd_api.hip -- the C ABI of libsrmhd (declared in include/srmhd.h):
 // configuration checks, carving of the caller's work buffer, and the launch
-// sequence of the SSP-RK3 stages.  Host code only; every launch goes to the
+// sequence of the SSP-RK stages.  Host code only; every launch goes to the
 // caller's stream.
 #include "srmhd.h"
 #include "srmhd_kernels.hpp"

@@ -1,13 +1,15 @@
-// srmhd_kernels.hip -- HIP kernels (gfx950) of one SSP-RK3 stage of 3D ideal
-// SRMHD on a periodic box, following the substep structure of Sec. 3 of
-// arXiv 2401.03008: INT + Newton inversion, REC + upwind face fluxes with
-// stored fast speeds, UCT edge fields, DER (flux divergence and curl) fused
-// with the Runge-Kutta update, and the once-per-step global speed maximum.
+// srmhd_kernels.hip -- HIP kernels (gfx950) of one SSP Runge-Kutta stage of
+// 3D ideal SRMHD on a periodic box, following the substep structure of Sec. 3
+// of arXiv 2401.03008: INT + Newton inversion (with the learned guess), REC +
+// upwind face fluxes with stored fast speeds, UCT edge fields, DER (flux
+// divergence and curl, second or sixth order) fused with the Runge-Kutta
+// update, and the once-per-step global speed maximum; plus the diagnostics
+// reductions and the training-pair harvest.
 //
-// Layout: structure of arrays, x fastest; a workgroup is 4 wavefronts, each
-// covering 64 consecutive x cells of one (y, z) row, so every global access of
-// a wavefront is a contiguous 512-byte (FP64) or 256-byte (FP32) segment.
-// Periodic wrap replaces ghost cells.
+// Layout: structure of arrays, x fastest; a workgroup is a tile of 64 x BY x
+// BZ cells, one wavefront per 64 consecutive x cells of a (y, z) row, so every
+// global access of a wavefront is a contiguous 512-byte (FP64) or 256-byte
+// (FP32) segment.  Periodic wrap replaces ghost cells.
 #include "srmhd_kernels.hpp"
 #include "srmhd_phys.hpp"
 
@@ -134,12 +136,6 @@ __device__ __forceinline__ int minus1(const GridDims& g, const Cell& c, int dir)
   if (dir == 0) return c.i == 0 ? c.id + g.nx - 1 : c.id - 1;
   if (dir == 1) return c.j == 0 ? c.id + (g.ny - 1) * g.nx : c.id - g.nx;
   return c.k == 0 ? c.id + (g.nz - 1) * g.nx * g.ny : c.id - g.nx * g.ny;
-}
-
-__device__ __forceinline__ int plus1(const GridDims& g, const Cell& c, int dir) {
-  if (dir == 0) return c.i == g.nx - 1 ? c.id - (g.nx - 1) : c.id + 1;
-  if (dir == 1) return c.j == g.ny - 1 ? c.id - (g.ny - 1) * g.nx : c.id + g.nx;
-  return c.k == g.nz - 1 ? c.id - (g.nz - 1) * g.nx * g.ny : c.id + g.nx * g.ny;
 }
 
 // INT: centred B_d of the cell from the face array bfd: the mean of the two

@@ -93,9 +93,16 @@ __device__ __forceinline__ bool face_state_ok(const FaceState<T>& s) {
 }
 
 // ---------------------------------------------------------------- MP5 (REC)
-// Suresh & Huynh (1997) monotonicity-preserving 5th-order interface value at
-// x_{i+1/2} from v_{i-2..i+2}, alpha = 4, eps = 1e-10.  The right state at the
-// same face is the mirror call mp5(v_{i+3}, v_{i+2}, v_{i+1}, v_i, v_{i-1}).
+// Suresh & Huynh (1997) monotonicity-preserving fifth-order interface values,
+// alpha = 4, eps = 1e-10.  Left state at x_{i+1/2} (centre v_i): the
+// unlimited fifth-order value v_or is kept when (v_or - v_i)(v_or - v_MP) <=
+// eps, v_MP = v_i + minmod(v_{i+1} - v_i, alpha (v_i - v_{i-1})); otherwise it
+// is limited to [v_min, v_max], the bounds built from v_i, v_{i+1}, the upper
+// limit v_UL = v_i + alpha (v_i - v_{i-1}), the median v_MD = (v_i +
+// v_{i+1})/2 - d^{M4}_{i+1/2}/2 and the large-curvature value v_LC = v_i +
+// (v_i - v_{i-1})/2 + (4/3) d^{M4}_{i-1/2}, with d^{M4} the minmod4 of the
+// neighbouring second differences.  The right state is the mirror image
+// (centre v_{i+1}, stencil reversed).
 
 // minmod(a, b) = (sgn a + sgn b)/2 * min(|a|, |b|) and
 // minmod4(a, b, c, d) = (sgn a + sgn b)/8 * |(sgn a + sgn c)(sgn a + sgn d)| *
@@ -116,33 +123,12 @@ __device__ __forceinline__ T minmod4(T a, T b, T c, T d) {
   return s * fmin(fmin(fabs(a), fabs(b)), fmin(fabs(c), fabs(d)));
 }
 
-template <typename T>
-__device__ __forceinline__ T mp5(T vm2, T vm1, T v0, T vp1, T vp2) {
-  // (2 v_{i-2} - 13 v_{i-1} + 47 v_i + 27 v_{i+1} - 3 v_{i+2}) / 60, written
-  // as v_i plus a combination of differences (exact on constant data)
-  const T vor = v0 + (T(2) * (vm2 - v0) - T(13) * (vm1 - v0) + T(27) * (vp1 - v0) -
-                      T(3) * (vp2 - v0)) * T(1.0 / 60.0);
-  const T dl = v0 - vm1;
-  const T vmp = v0 + minmod2(vp1 - v0, T(4) * dl);
-  if ((vor - v0) * (vor - vmp) <= T(1e-10)) return vor;
-  const T djm1 = vm2 - T(2) * vm1 + v0;
-  const T dj = vm1 - T(2) * v0 + vp1;
-  const T djp1 = v0 - T(2) * vp1 + vp2;
-  const T dm4p = minmod4(T(4) * dj - djp1, T(4) * djp1 - dj, dj, djp1);
-  const T dm4m = minmod4(T(4) * dj - djm1, T(4) * djm1 - dj, dj, djm1);
-  const T vul = v0 + T(4) * dl;
-  const T vmd = T(0.5) * (v0 + vp1) - T(0.5) * dm4p;
-  const T vlc = v0 + T(0.5) * dl + T(4.0 / 3.0) * dm4m;
-  const T vmin = fmax(fmin(fmin(v0, vp1), vmd), fmin(fmin(v0, vul), vlc));
-  const T vmax = fmin(fmax(fmax(v0, vp1), vmd), fmax(fmax(v0, vul), vlc));
-  return vor + minmod2(vmin - vor, vmax - vor);
-}
-
-// Both states at the face x_{i+1/2} from s[0..5] = v_{i-2..i+3}: left =
-// mp5(s0..s4), right = mp5(s5..s1).  Same arithmetic as two mp5 calls, but
-// the curvatures d_i, d_{i+1} and d^{M4}_{i+1/2} (minmod4 is symmetric in its
-// pair) are computed once for both sides, and only when a side needs its
-// limiter.  POINT: the unlimited value is the fifth-order interpolation of
+// Both states at the face x_{i+1/2} from s[0..5] = v_{i-2..i+3}: left from
+// s0..s4 (centre s2), right from s5..s1 (centre s3).  The curvatures d_i,
+// d_{i+1} and d^{M4}_{i+1/2} (minmod4 is symmetric in its pair) are computed
+// once for both sides, and only when a side needs its limiter.  The unlimited
+// value is written as the centre plus a combination of differences (exact on
+// constant data).  POINT: the unlimited value is the fifth-order interpolation of
 // point values, (3, -20, 90, 60, -5)/128 (the face point values that the
 // sixth-order DER expects), instead of the cell-average kernel.
 template <typename T, bool POINT = false>
