@@ -765,17 +765,23 @@ __device__ __forceinline__ void update_cell(const UpdArgs<TS>& a, const Cell& c)
 // The HO form has its own kernel for thin boxes (chosen on the host), so the
 // common case keeps a schedule with all stencil loads in flight together (a
 // run-time branch between the two index forms serialised them).
+// Tiles: 64x4x1; the HO form reads six-point stencils in all three
+// directions and takes 64x2x4 (FP64 fluxes) or 64x4x4 (FP32), 2% and 4%
+// faster than 64x4x1 at 256^3.
+template <bool HO, typename TS>
+using UpdTile = Tile<HO ? (sizeof(TS) == 8 ? 2 : 4) : 4, HO ? 4 : 1>;
+
 template <int STAGE, typename TS, bool HO, bool THIN>
-__global__ __launch_bounds__(kThreads) void k_update(UpdArgs<TS> a) {
-  const Cell c = cell_of(a.g);
+__global__ __launch_bounds__((UpdTile<HO, TS>::kThreads)) void k_update(UpdArgs<TS> a) {
+  const Cell c = cell_of_tile<UpdTile<HO, TS>::kY, UpdTile<HO, TS>::kZ>(a.g);
   if (!c.valid) return;
   update_cell<STAGE, TS, HO, THIN>(a, c);
 }
 
 template <typename TS, bool HO, bool THIN>
 void launch_update_ho(int stage, const UpdArgs<TS>& a, hipStream_t s) {
-  const dim3 grid = cell_grid(a.g);
-  dim3 blk(kBlockX, kBlockY);
+  const dim3 grid = tile_grid<UpdTile<HO, TS>::kY, UpdTile<HO, TS>::kZ>(a.g);
+  const dim3 blk = tile_block<UpdTile<HO, TS>::kY, UpdTile<HO, TS>::kZ>();
   switch (stage) {
     case 0: hipLaunchKernelGGL((k_update<0, TS, HO, THIN>), grid, blk, 0, s, a); break;
     case 1: hipLaunchKernelGGL((k_update<1, TS, HO, THIN>), grid, blk, 0, s, a); break;
