@@ -240,3 +240,27 @@ def test_2d_turbulence_step_parity(kw, okw):
     assert abs(d["divb_max"] - div0) * dx < 1e-11
     if not okw.get("ho"):
         assert d["divb_max"] * dx < 1e-11
+
+
+def test_llf_with_ho_and_zero_steps():
+    """LLF fluxes with HO against the oracle (24^3 diagonal wave, 4 steps),
+    and step(0) leaving the state, time and step count untouched."""
+    n = 24
+    shape = (n, n, n)
+    prim5, bf, _ = I.cpa(n, diagonal=True)
+    S = _solver(shape, high_order=True, riemann="llf")
+    S.init(prim5, bf)
+    c0 = S.cons.clone()
+    S.step(0)
+    t0, st0, _ = S.time()
+    assert st0 == 0 and t0 == 0.0 and torch.equal(S.cons, c0)
+    S.step(4)
+    P = S.primitives().cpu().numpy()
+    S.close()
+    g = _oracle(shape, ho=1, riemann=1)
+    cons, W = g.init(prim5, bf)
+    bfo = [b.copy() for b in bf]
+    g.step(cons, bfo, W, 4)
+    Pr, _, _ = g.c2p(cons, bfo, W)
+    for q in range(8):
+        assert l1rel(P[q], Pr[q], SCALE[q]) <= 1e-12, q
