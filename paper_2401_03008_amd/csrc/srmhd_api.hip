@@ -212,7 +212,7 @@ void stage_uct_update(srmhd_ctx* c, const StageState& st, int stage, double* con
       a.e[d] = c->edge[d];
     }
     KTimer kt(c, 4);
-    launch_uct3<TS>(a, rec_kind(c), c->stream);
+    launch_uct<TS>(a, rec_kind(c), c->stream);
   }
   UpdArgs<TS> u;
   u.g = c->g;

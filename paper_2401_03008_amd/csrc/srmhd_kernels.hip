@@ -496,50 +496,123 @@ void launch_harvest(const HarvestArgs& a, hipStream_t s) {
 // Tile per direction: 64x4x1 for x and y; for z 64x1x4 in FP64 and 64x1x8
 // in FP32 (the wavefronts of a z tile share stencil planes).  Measured at
 // 256^3: the FP64 z tile takes 3% off the z pass, the FP32 one 20%; taller
-// FP64 tiles (64x16x1 for y, 64x1x8 or 64x1x16 for z) were slower.
-template <int DIR, typename TS>
-struct FluxTile : Tile<DIR == 2 ? 1 : 4, DIR == 2 ? (sizeof(TS) == 4 ? 8 : 4) : 1> {};
+// FP64 tiles (64x16x1 for y, 64x1x8 or 64x1x16 for z) were slower.  STAGED:
+// the stencil operands come from LDS (Stage); a box thinner than the z tile
+// (nz = 1: a 2D run) takes the z pass unstaged on 64x4x1 tiles, its operands
+// read directly through the periodic stencil indices.
+template <int DIR, typename TS, bool STAGED = true>
+struct FluxTile : Tile<(DIR == 2 && STAGED) ? 1 : 4,
+                       (DIR == 2 && STAGED) ? (sizeof(TS) == 4 ? 8 : 4) : 1> {};
 
-template <int DIR, typename TS, bool CFL, bool STATS, int REC>
-__global__ __launch_bounds__((FluxTile<DIR, TS>::kThreads)) void k_flux(FluxArgs<TS> a) {
+__device__ __forceinline__ int wrap_index(int p, int n) {
+  int r = p % n;
+  return r + (r < 0 ? n : 0);
+}
+
+// LDS staging of stencil operands: a tile of 64 x BY x BZ cells extended by
+// the 5-cell REC halo (offsets -2..+3) along D, x fastest.  Each value is
+// fetched once per workgroup instead of once per stencil lane, and the
+// periodic wrap is resolved once per staged cell.  for_each calls f(e, id)
+// for every staged slot e inside the box (id: its cell index); rows beyond a
+// ragged box edge are skipped (their lanes are invalid).  Stencil point m of
+// tile cell (tx, ty, tz) sits at base(tx, ty, tz) + m * kStride.
+template <int D, int BY, int BZ>
+struct Stage {
+  static constexpr int EX = kBlockX + (D == 0 ? 5 : 0);
+  static constexpr int EY = BY + (D == 1 ? 5 : 0);
+  static constexpr int EZ = BZ + (D == 2 ? 5 : 0);
+  static constexpr int N = EX * EY * EZ;
+  static constexpr int kStride = D == 0 ? 1 : (D == 1 ? EX : EX * EY);
+  static constexpr int kThreads = kBlockX * BY * BZ;
+
+  __device__ static int base() {
+    return ((int)threadIdx.z * EY + (int)threadIdx.y) * EX + (int)threadIdx.x;
+  }
+
+  template <typename F>
+  __device__ static void for_each(const GridDims& g, const Cell& c, F&& f) {
+    const int x0 = c.i - (int)threadIdx.x, y0 = c.j - (int)threadIdx.y, z0 = c.k - (int)threadIdx.z;
+    if (!(x0 < g.nx && y0 < g.ny && z0 < g.nz)) return;  // a padding tile
+    const int tid = (int)threadIdx.x + kBlockX * ((int)threadIdx.y + BY * (int)threadIdx.z);
+#pragma unroll
+    for (int k = 0; k < (N + kThreads - 1) / kThreads; ++k) {
+      const int e = tid + k * kThreads;
+      if (e >= N) break;
+      int gx = x0 + e % EX, gy = y0 + (e / EX) % EY, gz = z0 + e / (EX * EY);
+      bool in;
+      if (D == 0) {
+        gx = wrap_index(gx - 2, g.nx);
+        in = gy < g.ny && gz < g.nz;
+      } else if (D == 1) {
+        gy = wrap_index(gy - 2, g.ny);
+        in = gx < g.nx && gz < g.nz;
+      } else {
+        gz = wrap_index(gz - 2, g.nz);
+        in = gx < g.nx && gy < g.ny;
+      }
+      if (in) f(e, (gz * g.ny + gy) * g.nx + gx);
+    }
+  }
+};
+
+template <int DIR, typename TS, bool CFL, bool STATS, int REC, bool STAGED>
+__global__ __launch_bounds__((FluxTile<DIR, TS, STAGED>::kThreads)) void k_flux(FluxArgs<TS> a) {
   using T = TS;
+  using Tl = FluxTile<DIR, TS, STAGED>;
+  using St = Stage<DIR, Tl::kY, Tl::kZ>;
   constexpr int T1 = (DIR + 1) % 3, T2 = (DIR + 2) % 3;
   __shared__ unsigned s_cnt[CNT_N];
   __shared__ double s_max[16];
+  __shared__ TS s_q[STAGED ? 7 : 1][STAGED ? St::N : 1];  // rho, v_n, v_t1, v_t2, p, B_t1, B_t2
   BlockCounters bc;
   if (STATS) bc.init(s_cnt);
-  const Cell c = cell_of_tile<FluxTile<DIR, TS>::kY, FluxTile<DIR, TS>::kZ>(a.g);
+  const Cell c = cell_of_tile<Tl::kY, Tl::kZ>(a.g);
+  const TS* q[7] = {a.prim[0], a.prim[1 + DIR], a.prim[1 + T1], a.prim[1 + T2],
+                    a.prim[4], a.prim[5 + T1],  a.prim[5 + T2]};
+  if constexpr (STAGED) {
+    St::for_each(a.g, c, [&](int e, int id) {
+#pragma unroll
+      for (int n = 0; n < 7; ++n) s_q[n][e] = q[n][id];
+    });
+    __syncthreads();
+  }
   int nfb = 0;
   double cfl_sum = 0.0;
   if (c.valid) {
+    // stencil point m (offset m - 2) of primitive n
     int idx[6];
-    stencil6(a.g, c, DIR, idx);
-    FaceState<T> L, R;
-    auto rec = [&](const TS* q, T& l, T& r) {
-      if (REC == kRecMc)  // the outer two stencil values are not read
-        rec_pair<REC, T>(T(0), q[idx[1]], q[idx[2]], q[idx[3]], q[idx[4]], T(0), l, r);
-      else
-        rec_pair<REC, T>(q[idx[0]], q[idx[1]], q[idx[2]], q[idx[3]], q[idx[4]], q[idx[5]], l, r);
+    if constexpr (!STAGED) stencil6(a.g, c, DIR, idx);
+    const int b = STAGED ? St::base() : 0;
+    auto val = [&](int n, int m) -> T {
+      if constexpr (STAGED) return s_q[n][b + m * St::kStride];
+      else return q[n][idx[m]];
     };
-    rec(a.prim[0], L.rho, R.rho);
-    rec(a.prim[1 + DIR], L.vn, R.vn);
-    rec(a.prim[1 + T1], L.vt1, R.vt1);
-    rec(a.prim[1 + T2], L.vt2, R.vt2);
-    rec(a.prim[4], L.p, R.p);
-    rec(a.prim[5 + T1], L.bt1, R.bt1);
-    rec(a.prim[5 + T2], L.bt2, R.bt2);
+    FaceState<T> L, R;
+    auto rec = [&](int n, T& l, T& r) {
+      if (REC == kRecMc)  // the outer two stencil values are not read
+        rec_pair<REC, T>(T(0), val(n, 1), val(n, 2), val(n, 3), val(n, 4), T(0), l, r);
+      else
+        rec_pair<REC, T>(val(n, 0), val(n, 1), val(n, 2), val(n, 3), val(n, 4), val(n, 5), l, r);
+    };
+    rec(0, L.rho, R.rho);
+    rec(1, L.vn, R.vn);
+    rec(2, L.vt1, R.vt1);
+    rec(3, L.vt2, R.vt2);
+    rec(4, L.p, R.p);
+    rec(5, L.bt1, R.bt1);
+    rec(6, L.bt2, R.bt2);
     const T bn = (T)a.bn[c.id];
     L.bn = R.bn = bn;
+    auto cell_state = [&](int m) {  // the unreconstructed state of stencil cell m
+      return FaceState<T>{val(0, m), val(1, m), val(2, m), val(3, m),
+                          val(4, m), bn,        val(5, m), val(6, m)};
+    };
     if (!face_state_ok(L)) {
-      const int m = idx[2];
-      L = FaceState<T>{a.prim[0][m], a.prim[1 + DIR][m], a.prim[1 + T1][m], a.prim[1 + T2][m],
-                       a.prim[4][m], bn, a.prim[5 + T1][m], a.prim[5 + T2][m]};
+      L = cell_state(2);
       ++nfb;
     }
     if (!face_state_ok(R)) {
-      const int m = idx[3];
-      R = FaceState<T>{a.prim[0][m], a.prim[1 + DIR][m], a.prim[1 + T1][m], a.prim[1 + T2][m],
-                       a.prim[4][m], bn, a.prim[5 + T1][m], a.prim[5 + T2][m]};
+      R = cell_state(3);
       ++nfb;
     }
     const T g = (T)a.gam, g1 = (T)(a.gam / (a.gam - 1.0));
@@ -602,24 +675,32 @@ __global__ __launch_bounds__((FluxTile<DIR, TS>::kThreads)) void k_flux(FluxArgs
   }
 }
 
-template <typename TS, int REC>
+template <typename TS, int REC, bool ZSTAGED>
 void launch_flux_rec(int dir, const FluxArgs<TS>& a, bool cfl, bool stats, hipStream_t s) {
-#define SRMHD_FLUX(D, C, S)                                                               \
-  hipLaunchKernelGGL((k_flux<D, TS, C, S, REC>),                                          \
-                     (tile_grid<FluxTile<D, TS>::kY, FluxTile<D, TS>::kZ>(a.g)),          \
-                     (tile_block<FluxTile<D, TS>::kY, FluxTile<D, TS>::kZ>()), 0, s, a)
+#define SRMHD_FLUX(D, C, S, G)                                                                  \
+  hipLaunchKernelGGL((k_flux<D, TS, C, S, REC, G>),                                             \
+                     (tile_grid<FluxTile<D, TS, G>::kY, FluxTile<D, TS, G>::kZ>(a.g)),          \
+                     (tile_block<FluxTile<D, TS, G>::kY, FluxTile<D, TS, G>::kZ>()), 0, s, a)
   if (dir == 0) {
-    if (stats) SRMHD_FLUX(0, false, true); else SRMHD_FLUX(0, false, false);
+    if (stats) SRMHD_FLUX(0, false, true, true); else SRMHD_FLUX(0, false, false, true);
   } else if (dir == 1) {
-    if (stats) SRMHD_FLUX(1, false, true); else SRMHD_FLUX(1, false, false);
+    if (stats) SRMHD_FLUX(1, false, true, true); else SRMHD_FLUX(1, false, false, true);
   } else {
     if (cfl) {
-      if (stats) SRMHD_FLUX(2, true, true); else SRMHD_FLUX(2, true, false);
+      if (stats) SRMHD_FLUX(2, true, true, ZSTAGED); else SRMHD_FLUX(2, true, false, ZSTAGED);
     } else {
-      if (stats) SRMHD_FLUX(2, false, true); else SRMHD_FLUX(2, false, false);
+      if (stats) SRMHD_FLUX(2, false, true, ZSTAGED); else SRMHD_FLUX(2, false, false, ZSTAGED);
     }
   }
 #undef SRMHD_FLUX
+}
+
+template <typename TS, int REC>
+void launch_flux_rec(int dir, const FluxArgs<TS>& a, bool cfl, bool stats, hipStream_t s) {
+  if (dir == 2 && a.g.nz < FluxTile<2, TS>::kZ)
+    launch_flux_rec<TS, REC, false>(dir, a, cfl, stats, s);
+  else
+    launch_flux_rec<TS, REC, true>(dir, a, cfl, stats, s);
 }
 
 template <typename TS>
@@ -636,81 +717,119 @@ template void launch_flux<float>(int, const FluxArgs<float>&, bool, bool, int, h
 // the two P-face velocity states (left/right along P) are MP5-reconstructed
 // along Q to the edge (corner states ab), B_P (P faces) along Q, B_Q (Q faces)
 // along P; E^{ab} = v_Q^{ab} B_P^b - v_P^{ab} B_Q^a (E = -v x B); edge speeds
-// are the maxima over the two adjacent faces of each direction.
-// One thread computes E_x, E_y and E_z of its cell.
-template <int K, int REC, typename TS>
-__device__ __forceinline__ double uct_one(const Uct3Args<TS>& a, int id, const int* const* st) {
+// are the maxima over the two adjacent faces of each direction.  REC runs in
+// the flux precision (FP32 in the mixed form, like the face reconstructions);
+// the edge formula stays FP64.
+//
+// One kernel per orientation K, on a tile that is long along Q (64x8x1 for
+// E_z, 64x1x8 for E_x and E_y): the five arrays reconstructed along Q (the
+// four P-face velocities and B_P) are staged in LDS with their Q halo, and
+// B_Q along P too where the tile is longer than one cell along P (E_z: x,
+// E_y: z); E_x reads B_z along y directly.  A box thinner than the tile
+// along Q (nz < 8 for E_x and E_y: a 2D run) takes the unstaged form on
+// 64x4x1 tiles, every operand read through the periodic stencil indices.
+template <int K, bool STAGED = true>
+struct UctTile : Tile<!STAGED ? 4 : (K == 2 ? 8 : 1), (!STAGED || K == 2) ? 1 : 8> {};
+
+__device__ __forceinline__ int plus1(const GridDims& g, const Cell& c, int dir) {
+  if (dir == 0) return c.i == g.nx - 1 ? c.id - (g.nx - 1) : c.id + 1;
+  if (dir == 1) return c.j == g.ny - 1 ? c.id - (g.ny - 1) * g.nx : c.id + g.nx;
+  return c.k == g.nz - 1 ? c.id - (g.nz - 1) * g.nx * g.ny : c.id + g.nx * g.ny;
+}
+
+template <int K, typename TS, int REC, bool STAGED>
+__global__ __launch_bounds__((UctTile<K, STAGED>::kThreads)) void k_uct(Uct3Args<TS> a) {
   constexpr int P = (K + 1) % 3, Q = (K + 2) % 3;
-  const int* iq = st[Q];
-  const int* ip = st[P];
-  // REC in the flux precision (FP32 in the mixed form, like the face
-  // reconstructions); the edge formula and the curl stay FP64
+  using Tl = UctTile<K, STAGED>;
+  using SQ = Stage<Q, Tl::kY, Tl::kZ>;
+  using SP = Stage<P, Tl::kY, Tl::kZ>;
+  constexpr bool kStageP = STAGED && (P == 0 ? kBlockX : (P == 1 ? Tl::kY : Tl::kZ)) > 1;
+  __shared__ TS s_q[STAGED ? 5 : 1][STAGED ? SQ::N : 1];  // left v_P, v_Q; right v_P, v_Q; B_P
+  __shared__ TS s_p[kStageP ? SP::N : 1];                 // B_Q
+  const Cell c = cell_of_tile<Tl::kY, Tl::kZ>(a.g);
+  if constexpr (STAGED) {
+    SQ::for_each(a.g, c, [&](int e, int id) {
+#pragma unroll
+      for (int n = 0; n < 4; ++n) s_q[n][e] = a.fv[P][n][id];
+      s_q[4][e] = (TS)a.bf[P][id];
+    });
+    if constexpr (kStageP) SP::for_each(a.g, c, [&](int e, int id) { s_p[e] = (TS)a.bf[Q][id]; });
+    __syncthreads();
+  }
+  if (!c.valid) return;
+  int iq[6], ip[6];
+  if constexpr (!STAGED) stencil6(a.g, c, Q, iq);
+  if constexpr (!kStageP) stencil6(a.g, c, P, ip);
+  const int bq = STAGED ? SQ::base() : 0, bp = kStageP ? SP::base() : 0;
+  // stencil point m (offset m - 2) along Q of array n (0..3: the P-face
+  // velocities, 4: B_P), and along P of B_Q
+  auto qv = [&](int n, int m) -> TS {
+    if constexpr (STAGED) return s_q[n][bq + m * SQ::kStride];
+    else return n < 4 ? a.fv[P][n][iq[m]] : (TS)a.bf[P][iq[m]];
+  };
+  auto pv = [&](int m) -> TS {
+    if constexpr (kStageP) return s_p[bp + m * SP::kStride];
+    else return (TS)a.bf[Q][ip[m]];
+  };
   using R = TS;
-  auto rec = [&](auto q, const int* idx, double& l, double& r) {
+  auto rec = [&](auto v, double& l, double& r) {
     R lr, rr;
     if (REC == kRecMc)  // the outer two stencil values are not read
-      rec_pair<REC, R>(R(0), (R)q[idx[1]], (R)q[idx[2]], (R)q[idx[3]], (R)q[idx[4]], R(0), lr, rr);
+      rec_pair<REC, R>(R(0), v(1), v(2), v(3), v(4), R(0), lr, rr);
     else
-      rec_pair<REC, R>((R)q[idx[0]], (R)q[idx[1]], (R)q[idx[2]], (R)q[idx[3]], (R)q[idx[4]],
-                       (R)q[idx[5]], lr, rr);
+      rec_pair<REC, R>(v(0), v(1), v(2), v(3), v(4), v(5), lr, rr);
     l = (double)lr;
     r = (double)rr;
   };
   double vp[2][2], vq[2][2];
 #pragma unroll
   for (int sd = 0; sd < 2; ++sd) {
-    rec(a.fv[P][2 * sd], iq, vp[sd][0], vp[sd][1]);      // v_P
-    rec(a.fv[P][2 * sd + 1], iq, vq[sd][0], vq[sd][1]);  // v_Q, Q = P + 1 cyclically
+    rec([&](int m) { return qv(2 * sd, m); }, vp[sd][0], vp[sd][1]);      // v_P
+    rec([&](int m) { return qv(2 * sd + 1, m); }, vq[sd][0], vq[sd][1]);  // v_Q, Q = P + 1 cyclically
   }
   double bpL, bpR, bqL, bqR;
-  rec(a.bf[P], iq, bpL, bpR);
-  rec(a.bf[Q], ip, bqL, bqR);
-  const double app = fmax((double)a.ap[P][id], (double)a.ap[P][iq[3]]);
-  const double amp = fmax((double)a.am[P][id], (double)a.am[P][iq[3]]);
-  const double aqp = fmax((double)a.ap[Q][id], (double)a.ap[Q][ip[3]]);
-  const double aqm = fmax((double)a.am[Q][id], (double)a.am[Q][ip[3]]);
+  rec([&](int m) { return qv(4, m); }, bpL, bpR);
+  rec(pv, bqL, bqR);
+  const int iq1 = plus1(a.g, c, Q), ip1 = plus1(a.g, c, P);
+  const double app = fmax((double)a.ap[P][c.id], (double)a.ap[P][iq1]);
+  const double amp = fmax((double)a.am[P][c.id], (double)a.am[P][iq1]);
+  const double aqp = fmax((double)a.ap[Q][c.id], (double)a.ap[Q][ip1]);
+  const double aqm = fmax((double)a.am[Q][c.id], (double)a.am[Q][ip1]);
   double E[2][2];
 #pragma unroll
   for (int sa = 0; sa < 2; ++sa)
 #pragma unroll
     for (int sb = 0; sb < 2; ++sb)
       E[sa][sb] = vq[sa][sb] * (sb ? bpR : bpL) - vp[sa][sb] * (sa ? bqR : bqL);
-  return uct_edge<double>(E[0][0], E[0][1], E[1][0], E[1][1], app, amp, aqp, aqm, bqL, bqR,
-                          bpL, bpR);
+  a.e[K][c.id] = uct_edge<double>(E[0][0], E[0][1], E[1][0], E[1][1], app, amp, aqp, aqm, bqL,
+                                  bqR, bpL, bpR);
 }
-
-// The edge stencils run along all three directions.  FP64: 64x1x4 tiles
-// (1.3% faster than 64x4x1 at 256^3); FP32: 64x4x1 (64x2x2 and 64x1x4 the
-// same); 64x4x4 was slower.
-template <typename TS>
-using UctTile = Tile<sizeof(TS) == 8 ? 1 : 4, sizeof(TS) == 8 ? 4 : 1>;
-template <typename TS>
-constexpr bool kUctXRows = sizeof(TS) == 4;
 
 template <typename TS, int REC>
-__global__ __launch_bounds__(UctTile<TS>::kThreads) void k_uct3(Uct3Args<TS> a) {
-  const Cell c = cell_of_tile<UctTile<TS>::kY, UctTile<TS>::kZ, kUctXRows<TS>>(a.g);
-  if (!c.valid) return;
-  int sx[6], sy[6], sz[6];
-  stencil6(a.g, c, 0, sx);
-  stencil6(a.g, c, 1, sy);
-  stencil6(a.g, c, 2, sz);
-  const int* st[3] = {sx, sy, sz};
-  a.e[2][c.id] = uct_one<2, REC>(a, c.id, st);
-  a.e[0][c.id] = uct_one<0, REC>(a, c.id, st);
-  a.e[1][c.id] = uct_one<1, REC>(a, c.id, st);
+void launch_uct_rec(const Uct3Args<TS>& a, hipStream_t s) {
+#define SRMHD_UCT(K, G)                                                                  \
+  hipLaunchKernelGGL((k_uct<K, TS, REC, G>),                                             \
+                     (tile_grid<UctTile<K, G>::kY, UctTile<K, G>::kZ>(a.g)),             \
+                     (tile_block<UctTile<K, G>::kY, UctTile<K, G>::kZ>()), 0, s, a)
+  if (a.g.ny >= UctTile<2>::kY) SRMHD_UCT(2, true); else SRMHD_UCT(2, false);
+  if (a.g.nz >= UctTile<0>::kZ) {
+    SRMHD_UCT(0, true);
+    SRMHD_UCT(1, true);
+  } else {
+    SRMHD_UCT(0, false);
+    SRMHD_UCT(1, false);
+  }
+#undef SRMHD_UCT
 }
 
 template <typename TS>
-void launch_uct3(const Uct3Args<TS>& a, int rec, hipStream_t s) {
-  const dim3 grid = tile_grid<UctTile<TS>::kY, UctTile<TS>::kZ, kUctXRows<TS>>(a.g);
-  const dim3 blk = tile_block<UctTile<TS>::kY, UctTile<TS>::kZ>();
-  if (rec == kRecMc) hipLaunchKernelGGL((k_uct3<TS, kRecMc>), grid, blk, 0, s, a);
-  else if (rec == kRecMp5Point) hipLaunchKernelGGL((k_uct3<TS, kRecMp5Point>), grid, blk, 0, s, a);
-  else hipLaunchKernelGGL((k_uct3<TS, kRecMp5>), grid, blk, 0, s, a);
+void launch_uct(const Uct3Args<TS>& a, int rec, hipStream_t s) {
+  if (rec == kRecMc) launch_uct_rec<TS, kRecMc>(a, s);
+  else if (rec == kRecMp5Point) launch_uct_rec<TS, kRecMp5Point>(a, s);
+  else launch_uct_rec<TS, kRecMp5>(a, s);
 }
-template void launch_uct3<double>(const Uct3Args<double>&, int, hipStream_t);
-template void launch_uct3<float>(const Uct3Args<float>&, int, hipStream_t);
+template void launch_uct<double>(const Uct3Args<double>&, int, hipStream_t);
+template void launch_uct<float>(const Uct3Args<float>&, int, hipStream_t);
 
 // -------------------------------------------------- DER + RK stage update
 // L(U) at centres: -sum_d (Fhat(+d face) - Fhat(-d face))/dx_d; at faces:
