@@ -43,30 +43,35 @@ STEP_BYTES_RK2 = 352.0
 # form, averaged over the class's launches in one step.  Bytes: every array
 # element the kernel must read or write, once.  flux: 7 primitives + normal B
 # in, 5 fluxes + a+- + 4 face velocities out (the z pass of stage 1 also reads
-# the x and y speeds for the CFL sum: (184 + 152 + 152)/3).  uct: 12 face
-# velocities + 6 speeds + 3 face B in, 3 edge fields out.  update: stage 1
-# reads 15 fluxes, 3 edge fields and U^n and writes the RK register; stages 2
-# and 3 also read U^n ((272 + 336 + 336)/3).  Flops: adds, multiplies,
-# divides and square roots of the formulas (FMA = 2), MP5 counted on its
-# limiter path (49 per call, 14 calls per face, 12 per edge; the UCT kernel
-# computes the three edges of a cell).
+# the x and y speeds for the CFL sum: (184 + 152 + 152)/3).  uct_k (one edge
+# orientation): the 4 velocities of the P faces, B_P and B_Q, and a+- of the
+# P and Q faces in, E_k out.  update: stage 1 reads 15 fluxes, 3 edge fields
+# and U^n and writes the RK register; stages 2 and 3 also read U^n ((272 +
+# 336 + 336)/3).  Flops: adds, multiplies, divides and square roots of the
+# formulas (FMA = 2), MP5 counted on its limiter path (49 per call, 14 calls
+# per face, 12 per edge).
 KERNEL_UNITS = {
     # class: (bytes fp64, bytes mixed, flops per unit)
     "c2p": (144.0, 112.0, 200.0),
     "flux_x": (152.0, 80.0, 940.0),
     "flux_y": (152.0, 80.0, 940.0),
     "flux_z": (488.0 / 3, 256.0 / 3, 940.0),
-    "uct": (192.0, 120.0, 1920.0),
+    "uct_x": (88.0, 56.0, 640.0),
+    "uct_y": (88.0, 56.0, 640.0),
+    "uct_z": (88.0, 56.0, 640.0),
     "update": (944.0 / 3, 764.0 / 3, 80.0),
 }
 # rocprofv3 kernel names of each class's FP64 launches in one step (name,
 # launches per step), for the HBM traffic read from the profiles
 PROFILED_KERNEL = {
     "c2p": [("k_c2p<false, false>", 3)],
-    "flux_x": [("k_flux<0, double, false, false, 0>", 3)],
-    "flux_y": [("k_flux<1, double, false, false, 0>", 3)],
-    "flux_z": [("k_flux<2, double, true, false, 0>", 1), ("k_flux<2, double, false, false, 0>", 2)],
-    "uct": [("k_uct3<double, 0>", 3)],
+    "flux_x": [("k_flux<0, double, false, false, 0, true>", 3)],
+    "flux_y": [("k_flux<1, double, false, false, 0, true>", 3)],
+    "flux_z": [("k_flux<2, double, true, false, 0, true>", 1),
+               ("k_flux<2, double, false, false, 0, true>", 2)],
+    "uct_x": [("k_uct<0, double, 0, true>", 3)],
+    "uct_y": [("k_uct<1, double, 0, true>", 3)],
+    "uct_z": [("k_uct<2, double, 0, true>", 3)],
     "update": [("k_update<1, double, false, false>", 1), ("k_update<2, double, false, false>", 1),
                ("k_update<3, double, false, false>", 1)],
 }

@@ -178,9 +178,9 @@ int srmhd_set_time(srmhd_ctx *ctx, double t, long step);
 
 /* Per-kernel timing with HIP events recorded on the context's stream around
  * every launch (adds a small host/queue overhead per launch; off by
- * default).  Classes, in order: 0 inversion, 1-3 face flux x/y/z, 4 UCT
- * edge fields (all three orientations; 5, 6 unused), 7 RK update, 8
- * timestep (the learned guess's inference is part of class 0).
+ * default).  Classes, in order: 0 inversion, 1-3 face flux x/y/z, 4-6 UCT
+ * edge fields E_x/E_y/E_z, 7 RK update, 8 timestep (the learned guess's
+ * inference is part of class 0).
  * srmhd_get_kernel_times syncs and
  * returns the accumulated milliseconds and launch counts since timing was
  * last enabled (ms, launches: host arrays of SRMHD_NKCLASS). */

@@ -251,7 +251,7 @@ def srmhd_mlp_adam(params, w_bf16, m, v, grad, n, lr, beta1, beta2, eps, t, stre
 
 
 NKCLASS = 9
-KCLASS_NAMES = ["c2p", "flux_x", "flux_y", "flux_z", "uct", "unused5", "unused6",
+KCLASS_NAMES = ["c2p", "flux_x", "flux_y", "flux_z", "uct_x", "uct_y", "uct_z",
                 "update", "dt"]
 
 

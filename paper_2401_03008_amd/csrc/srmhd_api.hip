@@ -211,8 +211,10 @@ void stage_uct_update(srmhd_ctx* c, const StageState& st, int stage, double* con
       a.bf[d] = st.bf[d];
       a.e[d] = c->edge[d];
     }
-    KTimer kt(c, 4);
-    launch_uct<TS>(a, rec_kind(c), c->stream);
+    for (int k = 0; k < 3; ++k) {
+      KTimer kt(c, 4 + k);
+      launch_uct<TS>(a, k, rec_kind(c), c->stream);
+    }
   }
   UpdArgs<TS> u;
   u.g = c->g;

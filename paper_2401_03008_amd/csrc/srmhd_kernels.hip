@@ -806,30 +806,29 @@ __global__ __launch_bounds__((UctTile<K, STAGED>::kThreads)) void k_uct(Uct3Args
 }
 
 template <typename TS, int REC>
-void launch_uct_rec(const Uct3Args<TS>& a, hipStream_t s) {
+void launch_uct_rec(const Uct3Args<TS>& a, int k, hipStream_t s) {
 #define SRMHD_UCT(K, G)                                                                  \
   hipLaunchKernelGGL((k_uct<K, TS, REC, G>),                                             \
                      (tile_grid<UctTile<K, G>::kY, UctTile<K, G>::kZ>(a.g)),             \
                      (tile_block<UctTile<K, G>::kY, UctTile<K, G>::kZ>()), 0, s, a)
-  if (a.g.ny >= UctTile<2>::kY) SRMHD_UCT(2, true); else SRMHD_UCT(2, false);
-  if (a.g.nz >= UctTile<0>::kZ) {
-    SRMHD_UCT(0, true);
-    SRMHD_UCT(1, true);
+  if (k == 2) {
+    if (a.g.ny >= UctTile<2>::kY) SRMHD_UCT(2, true); else SRMHD_UCT(2, false);
+  } else if (k == 0) {
+    if (a.g.nz >= UctTile<0>::kZ) SRMHD_UCT(0, true); else SRMHD_UCT(0, false);
   } else {
-    SRMHD_UCT(0, false);
-    SRMHD_UCT(1, false);
+    if (a.g.nz >= UctTile<1>::kZ) SRMHD_UCT(1, true); else SRMHD_UCT(1, false);
   }
 #undef SRMHD_UCT
 }
 
 template <typename TS>
-void launch_uct(const Uct3Args<TS>& a, int rec, hipStream_t s) {
-  if (rec == kRecMc) launch_uct_rec<TS, kRecMc>(a, s);
-  else if (rec == kRecMp5Point) launch_uct_rec<TS, kRecMp5Point>(a, s);
-  else launch_uct_rec<TS, kRecMp5>(a, s);
+void launch_uct(const Uct3Args<TS>& a, int k, int rec, hipStream_t s) {
+  if (rec == kRecMc) launch_uct_rec<TS, kRecMc>(a, k, s);
+  else if (rec == kRecMp5Point) launch_uct_rec<TS, kRecMp5Point>(a, k, s);
+  else launch_uct_rec<TS, kRecMp5>(a, k, s);
 }
-template void launch_uct<double>(const Uct3Args<double>&, int, hipStream_t);
-template void launch_uct<float>(const Uct3Args<float>&, int, hipStream_t);
+template void launch_uct<double>(const Uct3Args<double>&, int, int, hipStream_t);
+template void launch_uct<float>(const Uct3Args<float>&, int, int, hipStream_t);
 
 // -------------------------------------------------- DER + RK stage update
 // L(U) at centres: -sum_d (Fhat(+d face) - Fhat(-d face))/dx_d; at faces:

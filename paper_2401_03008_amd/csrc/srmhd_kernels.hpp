@@ -153,7 +153,7 @@ void launch_harvest(const HarvestArgs& a, hipStream_t s);
 template <typename TS>
 void launch_flux(int dir, const FluxArgs<TS>& a, bool cfl, bool stats, int rec, hipStream_t s);
 template <typename TS>
-void launch_uct(const Uct3Args<TS>& a, int rec, hipStream_t s);
+void launch_uct(const Uct3Args<TS>& a, int k, int rec, hipStream_t s);  // orientation E_k
 template <typename TS>
 void launch_update(int stage, const UpdArgs<TS>& a, bool ho, hipStream_t s);
 void launch_dt(DevScalars* sc, double cfl, double dt_fixed, hipStream_t s);
