@@ -7,9 +7,10 @@
 // reductions and the training-pair harvest.
 //
 // Layout: structure of arrays, x fastest; a workgroup is a tile of 64 x BY x
-// BZ cells, one wavefront per 64 consecutive x cells of a (y, z) row, so every
-// global access of a wavefront is a contiguous 512-byte (FP64) or 256-byte
-// (FP32) segment.  Periodic wrap replaces ghost cells.
+// BZ cells, one wavefront per 64 consecutive x cells of a (y, z) row (16 x 4
+// cells in the FP64 flux and UCT kernels), so every global access of a
+// wavefront is a contiguous 512-byte (FP64) or 256-byte (FP32) segment, or
+// four 128-byte ones.  Periodic wrap replaces ghost cells.
 #include "srmhd_kernels.hpp"
 #include "srmhd_phys.hpp"
 
@@ -22,6 +23,7 @@ constexpr unsigned kErrC2P = 1u, kErrNonfinite = 2u, kErrDt = 4u, kErrPressure =
 // --------------------------------------------------------------- helpers
 struct Cell {
   int i, j, k, id;
+  int li, lj, lk;  // position in the tile
   bool valid;
 };
 
@@ -41,6 +43,17 @@ struct Cell {
 // last-level cache.)  Lanes past the end of the box have valid = false.
 constexpr int kXcds = 8;
 
+// x cells per wavefront (64: a wavefront is one x row of its tile).  The FP64
+// flux and UCT kernels use 16x4-cell wavefronts: MP5 needs its limiter near
+// the extremum surfaces of each field, and SIMT runs it for a whole
+// wavefront if one lane needs it; a compact wavefront crosses such a surface
+// less often (on the diagonal Alfven wave at 128^3, 75% of 64x1 wavefronts per field
+// and direction contain a limited cell, 23% of 16x4 ones).  Measured: FP64 +4%
+// per step at 256^3 (CPA and turbulence); the FP32 passes were 2-6% slower.
+constexpr int kWaveX = 64;
+template <typename TS>
+constexpr int kStencilWaveX = sizeof(TS) == 8 ? 16 : 64;
+
 template <int BY, int BZ>
 struct Tile {
   static constexpr int kY = BY, kZ = BZ, kThreads = kBlockX * BY * BZ;
@@ -49,7 +62,7 @@ struct Tile {
 // XROWS = false keeps the plain x-fastest order (tile L on XCD L mod 8); the
 // FP64 UCT pass measured 2.6% faster with it, every other pass as fast or
 // faster (the mixed form's update by 7%) with the grouped rows.
-template <int BY, int BZ, bool XROWS = true>
+template <int BY, int BZ, bool XROWS = true, int WX = kWaveX>
 __device__ __forceinline__ Cell cell_of_tile(const GridDims& g) {
   const int nbx = (g.nx + kBlockX - 1) / kBlockX, nby = (g.ny + BY - 1) / BY;
   const int nbz = (g.nz + BZ - 1) / BZ;
@@ -58,10 +71,22 @@ __device__ __forceinline__ Cell cell_of_tile(const GridDims& g) {
   const int row = XROWS ? (slot / nbx) * kXcds + L % kXcds : L / nbx;  // by + nby bz
   const int bx = slot % nbx;
   const int by = row % nby, bz = row / nby;
+  // Wavefront w (hardware lanes threadIdx.x) covers WXE x cells of RW tile
+  // rows, or one whole row where the box is thinner than the tile.
+  constexpr int R = BY * BZ;
+  constexpr int RW = (kBlockX / WX < R) ? kBlockX / WX : R;
+  constexpr int WXE = kBlockX / RW;
+  const bool blocks = RW > 1 && g.ny >= BY && g.nz >= BZ;
+  const int w = threadIdx.y + BY * threadIdx.z, l = threadIdx.x;
+  const int dx = blocks ? (w % RW) * WXE + l % WXE : l;
+  const int dr = blocks ? (w / RW) * RW + l / WXE : w;
   Cell c;
-  c.i = bx * kBlockX + threadIdx.x;
-  c.j = by * BY + threadIdx.y;
-  c.k = bz * BZ + threadIdx.z;
+  c.li = dx;
+  c.lj = dr % BY;
+  c.lk = dr / BY;
+  c.i = bx * kBlockX + c.li;
+  c.j = by * BY + c.lj;
+  c.k = bz * BZ + c.lk;
   c.valid = bz < nbz && c.i < g.nx && c.j < g.ny && c.k < g.nz;
   c.id = c.valid ? (c.k * g.ny + c.j) * g.nx + c.i : 0;
   return c;
@@ -525,13 +550,11 @@ struct Stage {
   static constexpr int kStride = D == 0 ? 1 : (D == 1 ? EX : EX * EY);
   static constexpr int kThreads = kBlockX * BY * BZ;
 
-  __device__ static int base() {
-    return ((int)threadIdx.z * EY + (int)threadIdx.y) * EX + (int)threadIdx.x;
-  }
+  __device__ static int base(const Cell& c) { return (c.lk * EY + c.lj) * EX + c.li; }
 
   template <typename F>
   __device__ static void for_each(const GridDims& g, const Cell& c, F&& f) {
-    const int x0 = c.i - (int)threadIdx.x, y0 = c.j - (int)threadIdx.y, z0 = c.k - (int)threadIdx.z;
+    const int x0 = c.i - c.li, y0 = c.j - c.lj, z0 = c.k - c.lk;
     if (!(x0 < g.nx && y0 < g.ny && z0 < g.nz)) return;  // a padding tile
     const int tid = (int)threadIdx.x + kBlockX * ((int)threadIdx.y + BY * (int)threadIdx.z);
 #pragma unroll
@@ -566,7 +589,7 @@ __global__ __launch_bounds__((FluxTile<DIR, TS, STAGED>::kThreads)) void k_flux(
   __shared__ TS s_q[STAGED ? 7 : 1][STAGED ? St::N : 1];  // rho, v_n, v_t1, v_t2, p, B_t1, B_t2
   BlockCounters bc;
   if (STATS) bc.init(s_cnt);
-  const Cell c = cell_of_tile<Tl::kY, Tl::kZ>(a.g);
+  const Cell c = cell_of_tile<Tl::kY, Tl::kZ, true, kStencilWaveX<TS>>(a.g);
   const TS* q[7] = {a.prim[0], a.prim[1 + DIR], a.prim[1 + T1], a.prim[1 + T2],
                     a.prim[4], a.prim[5 + T1],  a.prim[5 + T2]};
   if constexpr (STAGED) {
@@ -582,7 +605,7 @@ __global__ __launch_bounds__((FluxTile<DIR, TS, STAGED>::kThreads)) void k_flux(
     // stencil point m (offset m - 2) of primitive n
     int idx[6];
     if constexpr (!STAGED) stencil6(a.g, c, DIR, idx);
-    const int b = STAGED ? St::base() : 0;
+    const int b = STAGED ? St::base(c) : 0;
     auto val = [&](int n, int m) -> T {
       if constexpr (STAGED) return s_q[n][b + m * St::kStride];
       else return q[n][idx[m]];
@@ -746,7 +769,7 @@ __global__ __launch_bounds__((UctTile<K, STAGED>::kThreads)) void k_uct(Uct3Args
   constexpr bool kStageP = STAGED && (P == 0 ? kBlockX : (P == 1 ? Tl::kY : Tl::kZ)) > 1;
   __shared__ TS s_q[STAGED ? 5 : 1][STAGED ? SQ::N : 1];  // left v_P, v_Q; right v_P, v_Q; B_P
   __shared__ TS s_p[kStageP ? SP::N : 1];                 // B_Q
-  const Cell c = cell_of_tile<Tl::kY, Tl::kZ>(a.g);
+  const Cell c = cell_of_tile<Tl::kY, Tl::kZ, true, kStencilWaveX<TS>>(a.g);
   if constexpr (STAGED) {
     SQ::for_each(a.g, c, [&](int e, int id) {
 #pragma unroll
@@ -760,7 +783,7 @@ __global__ __launch_bounds__((UctTile<K, STAGED>::kThreads)) void k_uct(Uct3Args
   int iq[6], ip[6];
   if constexpr (!STAGED) stencil6(a.g, c, Q, iq);
   if constexpr (!kStageP) stencil6(a.g, c, P, ip);
-  const int bq = STAGED ? SQ::base() : 0, bp = kStageP ? SP::base() : 0;
+  const int bq = STAGED ? SQ::base(c) : 0, bp = kStageP ? SP::base(c) : 0;
   // stencil point m (offset m - 2) along Q of array n (0..3: the P-face
   // velocities, 4: B_P), and along P of B_Q
   auto qv = [&](int n, int m) -> TS {

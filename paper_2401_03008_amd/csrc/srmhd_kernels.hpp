@@ -98,8 +98,8 @@ struct FluxArgs {
   unsigned long long* counters;
 };
 
-// All three edge orientations in one pass (each face-B and speed array is
-// used by two orientations).
+// Arrays of the edge-field kernels, for all three orientations (one launch
+// per orientation reads its share).
 template <typename TS>
 struct Uct3Args {
   GridDims g;
