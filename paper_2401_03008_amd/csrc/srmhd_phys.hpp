@@ -106,21 +106,19 @@ __device__ __forceinline__ bool face_state_ok(const FaceState<T>& s) {
 
 // minmod(a, b) = (sgn a + sgn b)/2 * min(|a|, |b|) and
 // minmod4(a, b, c, d) = (sgn a + sgn b)/8 * |(sgn a + sgn c)(sgn a + sgn d)| *
-// min(|a|, |b|, |c|, |d|): the common-sign minimum, else zero.  With sgn taken
-// as copysign(1, .) a zero argument makes the minimum zero, so both are exact
-// (the factors are 0 or +-1) and branch-free.
+// min(|a|, |b|, |c|, |d|): the argument of least magnitude when all have one
+// sign, else zero.  Written as max(min, 0) + min(max, 0) over the arguments:
+// all positive gives the minimum, all negative the maximum, mixed signs (or a
+// zero) give zero -- the same value exactly, in min/max instructions only.
 template <typename T>
 __device__ __forceinline__ T minmod2(T a, T b) {
-  const T s = T(0.5) * (copysign(T(1), a) + copysign(T(1), b));
-  return s * fmin(fabs(a), fabs(b));
+  return fmax(fmin(a, b), T(0)) + fmin(fmax(a, b), T(0));
 }
 
 template <typename T>
 __device__ __forceinline__ T minmod4(T a, T b, T c, T d) {
-  const T sa = copysign(T(1), a);
-  const T s = T(0.125) * (sa + copysign(T(1), b)) *
-              fabs((sa + copysign(T(1), c)) * (sa + copysign(T(1), d)));
-  return s * fmin(fmin(fabs(a), fabs(b)), fmin(fabs(c), fabs(d)));
+  const T lo = fmin(fmin(a, b), fmin(c, d)), hi = fmax(fmax(a, b), fmax(c, d));
+  return fmax(lo, T(0)) + fmin(hi, T(0));
 }
 
 // Both states at the face x_{i+1/2} from s[0..5] = v_{i-2..i+3}: left from
