@@ -65,6 +65,41 @@ def test_mixed_rhs_close_to_oracle():
         assert err <= 2e-5 * n, (q, err)
 
 
+@pytest.mark.parametrize("shape", [(12, 20, 72), (3, 20, 72), (12, 5, 72)])
+def test_mixed_rhs_ragged_and_thin_boxes(shape):
+    """The FP32 flux and edge-field kernels on ragged tiles (12 x 20 x 72:
+    no extent a multiple of the z or y tile) and on boxes thinner than a tile
+    (nz = 3, ny = 5: their unstaged forms), on a smooth turbulence state: L(U)
+    against the FP64 oracle.  FP32 face values carry ~6e-8 relative rounding;
+    L(U) is a difference of nearly uniform face fluxes, which amplifies it (an
+    L1 error of ~2e-5 of the component's L1 norm on this state).  The bounds
+    sit between that and what a mis-indexed stencil or a wrong halo gives
+    (errors of order the field's own variation, 1e-1 and up)."""
+    from paper_2401_03008_amd.solver import Solver
+    nz, ny, nx = shape
+    print(f"[gpu] mixed rhs {nx}x{ny}x{nz}", flush=True)
+    prim5, bf = I.turbulence((nx, ny, nz), gamma_max=2.0)
+    S = Solver(nx, ny, nz, precision="mixed")
+    S.init(prim5, bf)
+    R, amax = S.rhs()
+    R = R.cpu().numpy()
+    S.close()
+    g = O.Grid(nx, ny, nz)
+    cons, W = g.init(prim5, bf)
+    Pr, _, nf = g.c2p(cons, bf, W)
+    assert nf == 0
+    Rr, amax_r = g.rhs(Pr, bf)
+    assert amax.item() == pytest.approx(amax_r, rel=1e-5)
+    errs = []
+    for q in range(8):
+        e1 = np.abs(R[q] - Rr[q]).sum() / np.abs(Rr[q]).sum()
+        emax = np.abs(R[q] - Rr[q]).max() / np.abs(Rr[q]).max()
+        errs.append((e1, emax))
+    print("[gpu] mixed L(U) vs oracle (L1 rel, max rel):", ["%.1e/%.1e" % e for e in errs], flush=True)
+    for q, (e1, emax) in enumerate(errs):
+        assert e1 <= 1e-3 and emax <= 1e-2, (q, e1, emax)
+
+
 def test_mixed_vs_oracle_64_and_vs_exact():
     """Diagonal CPA at 64^3, 200 steps at the oracle's first FP64 dt: the
     mixed form's L1 error against the FP64 oracle is stated per variable and
