@@ -72,8 +72,8 @@ PROFILED_KERNEL = {
     "uct_x": [("k_uct<0, double, 0, true>", 3)],
     "uct_y": [("k_uct<1, double, 0, true>", 3)],
     "uct_z": [("k_uct<2, double, 0, true>", 3)],
-    "update": [("k_update<1, double, false, false>", 1), ("k_update<2, double, false, false>", 1),
-               ("k_update<3, double, false, false>", 1)],
+    "update": [("k_update<1, double>", 1), ("k_update<2, double>", 1),
+               ("k_update<3, double>", 1)],
 }
 
 

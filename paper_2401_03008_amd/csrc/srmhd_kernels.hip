@@ -535,13 +535,14 @@ __device__ __forceinline__ int wrap_index(int p, int n) {
 }
 
 // LDS staging of stencil operands: a tile of 64 x BY x BZ cells extended by
-// the 5-cell REC halo (offsets -2..+3) along D, x fastest.  Each value is
-// fetched once per workgroup instead of once per stencil lane, and the
-// periodic wrap is resolved once per staged cell.  for_each calls f(e, id)
-// for every staged slot e inside the box (id: its cell index); rows beyond a
-// ragged box edge are skipped (their lanes are invalid).  Stencil point m of
-// tile cell (tx, ty, tz) sits at base(tx, ty, tz) + m * kStride.
-template <int D, int BY, int BZ>
+// a 5-cell halo along D (six-point stencils at offsets LO..LO+5: -2..+3 for
+// REC, -3..+2 for the sixth-order differences of face values), x fastest.
+// Each value is fetched once per workgroup instead of once per stencil lane,
+// and the periodic wrap is resolved once per staged cell.  for_each calls
+// f(e, id) for every staged slot e inside the box (id: its cell index); rows
+// beyond a ragged box edge are skipped (their lanes are invalid).  Stencil
+// point m of tile cell c sits at base(c) + m * kStride.
+template <int D, int BY, int BZ, int LO = -2>
 struct Stage {
   static constexpr int EX = kBlockX + (D == 0 ? 5 : 0);
   static constexpr int EY = BY + (D == 1 ? 5 : 0);
@@ -564,13 +565,13 @@ struct Stage {
       int gx = x0 + e % EX, gy = y0 + (e / EX) % EY, gz = z0 + e / (EX * EY);
       bool in;
       if (D == 0) {
-        gx = wrap_index(gx - 2, g.nx);
+        gx = wrap_index(gx + LO, g.nx);
         in = gy < g.ny && gz < g.nz;
       } else if (D == 1) {
-        gy = wrap_index(gy - 2, g.ny);
+        gy = wrap_index(gy + LO, g.ny);
         in = gx < g.nx && gz < g.nz;
       } else {
-        gz = wrap_index(gz - 2, g.nz);
+        gz = wrap_index(gz + LO, g.nz);
         in = gx < g.nx && gy < g.ny;
       }
       if (in) f(e, (gz * g.ny + gy) * g.nx + gx);
@@ -862,43 +863,10 @@ template void launch_uct<float>(const Uct3Args<float>&, int, int, hipStream_t);
 // SSP-RK2: stage 1, then stage 4: U^{n+1} = 1/2 U^n + 1/2 (U1 + dt L(U1)).
 // Stage 0 writes L only.  Stage 1 writes U1 to a work register, so U^n stays
 // in the caller's arrays and is read back by the later stages (no copy).
-template <int STAGE, typename TS, bool HO, bool THIN>
-__device__ __forceinline__ void update_cell(const UpdArgs<TS>& a, const Cell& c) {
-  const double* ix = a.g.inv_dx;
-  const double* Ex = a.e[0];
-  const double* Ey = a.e[1];
-  const double* Ez = a.e[2];
-  double r[8];
-  if (HO) {
-    int s[3][6];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) stencil6_t<THIN>(a.g, c, d, -3, s[d]);
-#pragma unroll
-    for (int n = 0; n < 5; ++n) {
-      double acc = 0.0;
-#pragma unroll
-      for (int d = 0; d < 3; ++d) acc += der6_at(a.fhat[d][n], s[d]) * ix[d];
-      r[n] = -acc;
-    }
-    r[5] = -(der6_at(Ez, s[1]) * ix[1] - der6_at(Ey, s[2]) * ix[2]);
-    r[6] = -(der6_at(Ex, s[2]) * ix[2] - der6_at(Ez, s[0]) * ix[0]);
-    r[7] = -(der6_at(Ey, s[0]) * ix[0] - der6_at(Ex, s[1]) * ix[1]);
-  } else {
-    const int im = minus1(a.g, c, 0), jm = minus1(a.g, c, 1), km = minus1(a.g, c, 2);
-    const int nb[3] = {im, jm, km};
-#pragma unroll
-    for (int n = 0; n < 5; ++n) {
-      double acc = 0.0;
-#pragma unroll
-      for (int d = 0; d < 3; ++d)
-        acc += ((double)a.fhat[d][n][c.id] - (double)a.fhat[d][n][nb[d]]) * ix[d];
-      r[n] = -acc;
-    }
-    const double ex0 = Ex[c.id], ey0 = Ey[c.id], ez0 = Ez[c.id];
-    r[5] = -((ez0 - Ez[jm]) * ix[1] - (ey0 - Ey[km]) * ix[2]);
-    r[6] = -((ex0 - Ex[km]) * ix[2] - (ez0 - Ez[im]) * ix[0]);
-    r[7] = -((ey0 - Ey[im]) * ix[0] - (ex0 - Ex[jm]) * ix[1]);
-  }
+
+// The stage's combination of U with L(U) = r (stage 0: store r instead).
+template <int STAGE, typename TS>
+__device__ __forceinline__ void rk_apply(const UpdArgs<TS>& a, const Cell& c, const double* r) {
   if (STAGE == 0) {
 #pragma unroll
     for (int n = 0; n < 8; ++n) a.rhs_out[n][c.id] = r[n];
@@ -920,41 +888,118 @@ __device__ __forceinline__ void update_cell(const UpdArgs<TS>& a, const Cell& c)
   }
 }
 
-// The HO form has its own kernel for thin boxes (chosen on the host), so the
-// common case keeps a schedule with all stencil loads in flight together (a
-// run-time branch between the two index forms serialised them).
-// Tiles: 64x4x1; the HO form reads six-point stencils in all three
-// directions and takes 64x2x4 (FP64 fluxes) or 64x4x4 (FP32), 2% and 4%
-// faster than 64x4x1 at 256^3.
-template <bool HO, typename TS>
-using UpdTile = Tile<HO ? (sizeof(TS) == 8 ? 2 : 4) : 4, HO ? 4 : 1>;
-
-template <int STAGE, typename TS, bool HO, bool THIN>
-__global__ __launch_bounds__((UpdTile<HO, TS>::kThreads)) void k_update(UpdArgs<TS> a) {
-  const Cell c = cell_of_tile<UpdTile<HO, TS>::kY, UpdTile<HO, TS>::kZ>(a.g);
+// Second-order DER: one-sided differences of the +face fluxes and edges.
+template <int STAGE, typename TS>
+__global__ __launch_bounds__(kThreads) void k_update(UpdArgs<TS> a) {
+  const Cell c = cell_of_tile<kBlockY, 1>(a.g);
   if (!c.valid) return;
-  update_cell<STAGE, TS, HO, THIN>(a, c);
+  const double* ix = a.g.inv_dx;
+  const double* Ex = a.e[0];
+  const double* Ey = a.e[1];
+  const double* Ez = a.e[2];
+  const int im = minus1(a.g, c, 0), jm = minus1(a.g, c, 1), km = minus1(a.g, c, 2);
+  const int nb[3] = {im, jm, km};
+  double r[8];
+#pragma unroll
+  for (int n = 0; n < 5; ++n) {
+    double acc = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+      acc += ((double)a.fhat[d][n][c.id] - (double)a.fhat[d][n][nb[d]]) * ix[d];
+    r[n] = -acc;
+  }
+  const double ex0 = Ex[c.id], ey0 = Ey[c.id], ez0 = Ez[c.id];
+  r[5] = -((ez0 - Ez[jm]) * ix[1] - (ey0 - Ey[km]) * ix[2]);
+  r[6] = -((ex0 - Ex[km]) * ix[2] - (ez0 - Ez[im]) * ix[0]);
+  r[7] = -((ey0 - Ey[im]) * ix[0] - (ex0 - Ex[jm]) * ix[1]);
+  rk_apply<STAGE>(a, c, r);
 }
 
-template <typename TS, bool HO, bool THIN>
-void launch_update_ho(int stage, const UpdArgs<TS>& a, hipStream_t s) {
-  const dim3 grid = tile_grid<UpdTile<HO, TS>::kY, UpdTile<HO, TS>::kZ>(a.g);
-  const dim3 blk = tile_block<UpdTile<HO, TS>::kY, UpdTile<HO, TS>::kZ>();
-  switch (stage) {
-    case 0: hipLaunchKernelGGL((k_update<0, TS, HO, THIN>), grid, blk, 0, s, a); break;
-    case 1: hipLaunchKernelGGL((k_update<1, TS, HO, THIN>), grid, blk, 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_update<2, TS, HO, THIN>), grid, blk, 0, s, a); break;
-    case 3: hipLaunchKernelGGL((k_update<3, TS, HO, THIN>), grid, blk, 0, s, a); break;
-    default: hipLaunchKernelGGL((k_update<4, TS, HO, THIN>), grid, blk, 0, s, a); break;
+// HO DER: sixth-order differences (der6) of the face fluxes and edge fields.
+// Each direction differentiates seven arrays: its five face fluxes and the
+// two edge fields it curls (x: E_z, E_y; y: E_z, E_x; z: E_y, E_x).  The x and
+// the y arrays pass through one LDS buffer in turn (Stage, offsets -3..+2);
+// the z arrays are read through the periodic indices (THINZ: the modulo form,
+// for nz < 4).  Each difference is taken once and the terms are summed in a
+// fixed order.  Tiles of 64x4x1.
+template <int STAGE, typename TS, bool THINZ>
+__global__ __launch_bounds__(kThreads) void k_update_ho(UpdArgs<TS> a) {
+  using SX = Stage<0, kBlockY, 1, -3>;
+  using SY = Stage<1, kBlockY, 1, -3>;
+  constexpr int NS = SX::N > SY::N ? SX::N : SY::N;
+  __shared__ double s_v[7 * NS];
+  const Cell c = cell_of_tile<kBlockY, 1>(a.g);
+  const double* ix = a.g.inv_dx;
+  double d6[3][7];  // [direction][5 fluxes, then the two edge fields above]
+  auto der6_lds = [&](const double* v, int k) {
+    return der6(v[0], v[k], v[2 * k], v[3 * k], v[4 * k], v[5 * k]);
+  };
+  SX::for_each(a.g, c, [&](int e, int id) {
+#pragma unroll
+    for (int n = 0; n < 5; ++n) s_v[n * NS + e] = (double)a.fhat[0][n][id];
+    s_v[5 * NS + e] = a.e[2][id];
+    s_v[6 * NS + e] = a.e[1][id];
+  });
+  __syncthreads();
+  if (c.valid) {
+    const int b = SX::base(c);
+#pragma unroll
+    for (int m = 0; m < 7; ++m) d6[0][m] = der6_lds(&s_v[m * NS + b], SX::kStride);
   }
+  __syncthreads();
+  SY::for_each(a.g, c, [&](int e, int id) {
+#pragma unroll
+    for (int n = 0; n < 5; ++n) s_v[n * NS + e] = (double)a.fhat[1][n][id];
+    s_v[5 * NS + e] = a.e[2][id];
+    s_v[6 * NS + e] = a.e[0][id];
+  });
+  __syncthreads();
+  if (!c.valid) return;
+  {
+    const int b = SY::base(c);
+#pragma unroll
+    for (int m = 0; m < 7; ++m) d6[1][m] = der6_lds(&s_v[m * NS + b], SY::kStride);
+  }
+  int sz[6];
+  stencil6_t<THINZ>(a.g, c, 2, -3, sz);
+#pragma unroll
+  for (int n = 0; n < 5; ++n) d6[2][n] = der6_at(a.fhat[2][n], sz);
+  d6[2][5] = der6_at(a.e[1], sz);
+  d6[2][6] = der6_at(a.e[0], sz);
+  double r[8];
+#pragma unroll
+  for (int n = 0; n < 5; ++n) {
+    double acc = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) acc += d6[d][n] * ix[d];
+    r[n] = -acc;
+  }
+  r[5] = -(d6[1][5] * ix[1] - d6[2][5] * ix[2]);
+  r[6] = -(d6[2][6] * ix[2] - d6[0][5] * ix[0]);
+  r[7] = -(d6[0][6] * ix[0] - d6[1][6] * ix[1]);
+  rk_apply<STAGE>(a, c, r);
 }
 
 template <typename TS>
 void launch_update(int stage, const UpdArgs<TS>& a, bool ho, hipStream_t s) {
-  const bool thin = a.g.nx < 4 || a.g.ny < 4 || a.g.nz < 4;
-  if (!ho) launch_update_ho<TS, false, false>(stage, a, s);
-  else if (thin) launch_update_ho<TS, true, true>(stage, a, s);
-  else launch_update_ho<TS, true, false>(stage, a, s);
+  const dim3 grid = tile_grid<kBlockY, 1>(a.g);
+  const dim3 blk = tile_block<kBlockY, 1>();
+#define SRMHD_UPD(K, ...)                                                  \
+  switch (stage) {                                                        \
+    case 0: hipLaunchKernelGGL((K<0, __VA_ARGS__>), grid, blk, 0, s, a); break; \
+    case 1: hipLaunchKernelGGL((K<1, __VA_ARGS__>), grid, blk, 0, s, a); break; \
+    case 2: hipLaunchKernelGGL((K<2, __VA_ARGS__>), grid, blk, 0, s, a); break; \
+    case 3: hipLaunchKernelGGL((K<3, __VA_ARGS__>), grid, blk, 0, s, a); break; \
+    default: hipLaunchKernelGGL((K<4, __VA_ARGS__>), grid, blk, 0, s, a); break; \
+  }
+  if (!ho) {
+    SRMHD_UPD(k_update, TS)
+  } else if (a.g.nz < 4) {
+    SRMHD_UPD(k_update_ho, TS, true)
+  } else {
+    SRMHD_UPD(k_update_ho, TS, false)
+  }
+#undef SRMHD_UPD
 }
 template void launch_update<double>(int, const UpdArgs<double>&, bool, hipStream_t);
 template void launch_update<float>(int, const UpdArgs<float>&, bool, hipStream_t);
