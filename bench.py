@@ -255,6 +255,9 @@ def main():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--stats", action="store_true", help="collect Newton statistics while timed")
+    ap.add_argument("--guess", default="prev", choices=["prev", "mlp"],
+                    help="Newton guess of the timed run: the previous W, or the learned "
+                         "network (trained first by the library's kernels)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--no-forms", action="store_true",
@@ -291,6 +294,12 @@ def main():
     S = Solver(n, precision=args.precision, collect_stats=args.stats)
     S.init(prim5, bf)
     del prim5, bf
+    if args.guess == "mlp":
+        from paper_2401_03008_amd.learned import train_default
+        net = train_default()[0]
+        S.set_mlp(net)
+        S.set_guess("mlp")
+        print("[bench] learned guess trained and set", file=sys.stderr, flush=True)
     S.step(args.warmup)
     torch.cuda.synchronize()
     print(f"[bench] warm-up done ({args.warmup} steps)", file=sys.stderr, flush=True)
@@ -393,7 +402,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"CPA Alfven wave on the box diagonal, {n}^3, FP64 state, "
                                f"MP5 + HLL + UCT + SSP-RK3, CFL 0.5",
-                   "cells": n ** 3, "precision": args.precision,
+                   "cells": n ** 3, "precision": args.precision, "guess": args.guess,
                    "newton_stats": bool(args.stats)},
         "hbm_roofline_frac_step": round(value * 1e6 * STEP_BYTES / (HBM_PEAK_GBS * 1e9), 4),
         "roofline": roof,
