@@ -255,6 +255,12 @@ def main():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--stats", action="store_true", help="collect Newton statistics while timed")
+    ap.add_argument("--high-order", action="store_true",
+                    help="HO: sixth-order INT and DER, point-value MP5 (the timed run; with "
+                         "this or --recon mc the roofline's flop counts stay those of the "
+                         "default scheme)")
+    ap.add_argument("--recon", default="mp5", choices=["mp5", "mc"])
+    ap.add_argument("--time-order", type=int, default=3, choices=[2, 3])
     ap.add_argument("--guess", default="prev", choices=["prev", "mlp"],
                     help="Newton guess of the timed run: the previous W, or the learned "
                          "network (trained first by the library's kernels)")
@@ -291,7 +297,11 @@ def main():
     n = args.n
     print(f"[bench] building the {n}^3 diagonal CPA", file=sys.stderr, flush=True)
     prim5, bf, _ = inputs.cpa(n, diagonal=True, device="cuda")
-    S = Solver(n, precision=args.precision, collect_stats=args.stats)
+    scheme = ("point-value MP5, sixth-order INT/DER" if args.high_order else
+              ("MP5" if args.recon == "mp5" else "linear MC"))
+    step_bytes = STEP_BYTES if args.time_order == 3 else STEP_BYTES_RK2
+    S = Solver(n, precision=args.precision, collect_stats=args.stats, recon=args.recon,
+               time_order=args.time_order, high_order=args.high_order)
     S.init(prim5, bf)
     del prim5, bf
     if args.guess == "mlp":
@@ -346,7 +356,9 @@ def main():
         else:
             roof = {"bound": "alu", "achieved": round(tfl, 3), "peak": fpeak,
                     "unit": "TFLOP/s", "frac": round(tfl / fpeak, 4), "traffic": None}
-        if args.precision == "fp64" and n == 256:
+        default_scheme = (not args.high_order and args.recon == "mp5" and args.time_order == 3
+                          and args.guess == "prev")
+        if args.precision == "fp64" and n == 256 and default_scheme:
             roof["traffic"] = profiled_traffic(dom)
         roof.update({"kernel": dom, "avg_ms": round(kernels[dom]["avg_ms"], 4),
                      "alg_bytes_per_launch": bytes_per, "alg_flops_per_launch": flops_per,
@@ -401,10 +413,10 @@ def main():
         "dtype": "f64" if args.precision == "fp64" else "f64 state + f32 REC/flux",
         "data": "synthetic",
         "config": {"workload": f"CPA Alfven wave on the box diagonal, {n}^3, FP64 state, "
-                               f"MP5 + HLL + UCT + SSP-RK3, CFL 0.5",
+                               f"{scheme} + HLL + UCT + SSP-RK{args.time_order}, CFL 0.5",
                    "cells": n ** 3, "precision": args.precision, "guess": args.guess,
                    "newton_stats": bool(args.stats)},
-        "hbm_roofline_frac_step": round(value * 1e6 * STEP_BYTES / (HBM_PEAK_GBS * 1e9), 4),
+        "hbm_roofline_frac_step": round(value * 1e6 * step_bytes / (HBM_PEAK_GBS * 1e9), 4),
         "roofline": roof,
         "cpu_baseline": cpu,
         "kernels": kernels,
