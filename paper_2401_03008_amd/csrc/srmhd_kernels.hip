@@ -59,16 +59,13 @@ struct Tile {
   static constexpr int kY = BY, kZ = BZ, kThreads = kBlockX * BY * BZ;
 };
 
-// XROWS = false keeps the plain x-fastest order (tile L on XCD L mod 8); the
-// FP64 UCT pass measured 2.6% faster with it, every other pass as fast or
-// faster (the mixed form's update by 7%) with the grouped rows.
-template <int BY, int BZ, bool XROWS = true, int WX = kWaveX>
+template <int BY, int BZ, int WX = kWaveX>
 __device__ __forceinline__ Cell cell_of_tile(const GridDims& g) {
   const int nbx = (g.nx + kBlockX - 1) / kBlockX, nby = (g.ny + BY - 1) / BY;
   const int nbz = (g.nz + BZ - 1) / BZ;
   const int L = blockIdx.x;
-  const int slot = XROWS ? L / kXcds : L;
-  const int row = XROWS ? (slot / nbx) * kXcds + L % kXcds : L / nbx;  // by + nby bz
+  const int slot = L / kXcds;
+  const int row = (slot / nbx) * kXcds + L % kXcds;  // by + nby bz
   const int bx = slot % nbx;
   const int by = row % nby, bz = row / nby;
   // Wavefront w (hardware lanes threadIdx.x) covers WXE x cells of RW tile
@@ -100,12 +97,12 @@ __device__ __forceinline__ int block_linear() { return blockIdx.x; }
 __device__ __forceinline__ int wave_in_block() { return threadIdx.z * blockDim.y + threadIdx.y; }
 __device__ __forceinline__ int waves_in_block() { return blockDim.y * blockDim.z; }
 
-// Grid of whole groups of kXcds tile rows (or just the tiles, without XROWS).
-template <int BY, int BZ, bool XROWS = true>
+// Grid of whole groups of kXcds tile rows.
+template <int BY, int BZ>
 inline dim3 tile_grid(const GridDims& g) {
   const long long nbx = (g.nx + kBlockX - 1) / kBlockX;
   const long long rows = (long long)((g.ny + BY - 1) / BY) * ((g.nz + BZ - 1) / BZ);
-  return dim3((unsigned)((XROWS ? (rows + kXcds - 1) / kXcds * kXcds : rows) * nbx));
+  return dim3((unsigned)((rows + kXcds - 1) / kXcds * kXcds * nbx));
 }
 
 template <int BY, int BZ>
@@ -590,7 +587,7 @@ __global__ __launch_bounds__((FluxTile<DIR, TS, STAGED>::kThreads)) void k_flux(
   __shared__ TS s_q[STAGED ? 7 : 1][STAGED ? St::N : 1];  // rho, v_n, v_t1, v_t2, p, B_t1, B_t2
   BlockCounters bc;
   if (STATS) bc.init(s_cnt);
-  const Cell c = cell_of_tile<Tl::kY, Tl::kZ, true, kStencilWaveX<TS>>(a.g);
+  const Cell c = cell_of_tile<Tl::kY, Tl::kZ, kStencilWaveX<TS>>(a.g);
   const TS* q[7] = {a.prim[0], a.prim[1 + DIR], a.prim[1 + T1], a.prim[1 + T2],
                     a.prim[4], a.prim[5 + T1],  a.prim[5 + T2]};
   if constexpr (STAGED) {
@@ -770,7 +767,7 @@ __global__ __launch_bounds__((UctTile<K, STAGED>::kThreads)) void k_uct(Uct3Args
   constexpr bool kStageP = STAGED && (P == 0 ? kBlockX : (P == 1 ? Tl::kY : Tl::kZ)) > 1;
   __shared__ TS s_q[STAGED ? 5 : 1][STAGED ? SQ::N : 1];  // left v_P, v_Q; right v_P, v_Q; B_P
   __shared__ TS s_p[kStageP ? SP::N : 1];                 // B_Q
-  const Cell c = cell_of_tile<Tl::kY, Tl::kZ, true, kStencilWaveX<TS>>(a.g);
+  const Cell c = cell_of_tile<Tl::kY, Tl::kZ, kStencilWaveX<TS>>(a.g);
   if constexpr (STAGED) {
     SQ::for_each(a.g, c, [&](int e, int id) {
 #pragma unroll
@@ -1067,7 +1064,12 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce_partial(ReduceArgs a)
     const int i = id % a.g.nx, j = (id / a.g.nx) % a.g.ny, k = id / nxy;
     double dv = 0.0;
     if (a.ho) {
-      const Cell c{i, j, k, id, true};
+      Cell c{};
+      c.i = i;
+      c.j = j;
+      c.k = k;
+      c.id = id;
+      c.valid = true;
       int s[6];
       for (int d = 0; d < 3; ++d) {
         stencil6_from(a.g, c, d, -3, s);
