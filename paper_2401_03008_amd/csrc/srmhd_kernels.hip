@@ -977,6 +977,66 @@ __global__ __launch_bounds__(kThreads) void k_update_ho(UpdArgs<TS> a) {
   rk_apply<STAGE>(a, c, r);
 }
 
+// One staging phase of the 3D HO update: arrays M0..M0+CNT-1 of direction D
+// (0..4: the D face fluxes, 5, 6: the two edge fields D curls) through the
+// LDS buffer, their sixth-order differences into d6[D][M].
+template <int D, int M0, int CNT, int BY, int BZ, typename TS>
+__device__ __forceinline__ void ho_phase(const UpdArgs<TS>& a, const Cell& c, double* s_v,
+                                         double (&d6)[3][7]) {
+  using S = Stage<D, BY, BZ, -3>;
+  constexpr int E5 = D == 2 ? 1 : 2, E6 = D == 0 ? 1 : 0;  // x: E_z, E_y; y: E_z, E_x; z: E_y, E_x
+  S::for_each(a.g, c, [&](int e, int id) {
+#pragma unroll
+    for (int j = 0; j < CNT; ++j) {
+      const int m = M0 + j;
+      s_v[j * S::N + e] = m < 5 ? (double)a.fhat[D][m][id] : a.e[m == 5 ? E5 : E6][id];
+    }
+  });
+  __syncthreads();
+  if (c.valid) {
+    const int b = S::base(c);
+#pragma unroll
+    for (int j = 0; j < CNT; ++j) {
+      const double* v = &s_v[j * S::N + b];
+      constexpr int k = S::kStride;
+      d6[D][M0 + j] = der6(v[0], v[k], v[2 * k], v[3 * k], v[4 * k], v[5 * k]);
+    }
+  }
+  __syncthreads();
+}
+
+// The HO update on 64x4x4 tiles (boxes with nz >= 4): all three directions
+// staged, the y and z arrays in two batches (4 + 3) so that one 72 KB buffer
+// serves every phase.  Same differences and the same sums as k_update_ho.
+template <int STAGE, typename TS>
+__global__ __launch_bounds__(kBlockX * 16) void k_update_ho3(UpdArgs<TS> a) {
+  constexpr int NX = Stage<0, 4, 4, -3>::N, NY = Stage<1, 4, 4, -3>::N, NZ = Stage<2, 4, 4, -3>::N;
+  constexpr int NXS = 7 * NX, NYS = 4 * NY, NZS = 4 * NZ;
+  constexpr int NS = NXS > NYS ? (NXS > NZS ? NXS : NZS) : (NYS > NZS ? NYS : NZS);
+  __shared__ double s_v[NS];
+  const Cell c = cell_of_tile<4, 4>(a.g);
+  double d6[3][7];
+  ho_phase<0, 0, 7, 4, 4>(a, c, s_v, d6);
+  ho_phase<1, 0, 4, 4, 4>(a, c, s_v, d6);
+  ho_phase<1, 4, 3, 4, 4>(a, c, s_v, d6);
+  ho_phase<2, 0, 4, 4, 4>(a, c, s_v, d6);
+  ho_phase<2, 4, 3, 4, 4>(a, c, s_v, d6);
+  if (!c.valid) return;
+  const double* ix = a.g.inv_dx;
+  double r[8];
+#pragma unroll
+  for (int n = 0; n < 5; ++n) {
+    double acc = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) acc += d6[d][n] * ix[d];
+    r[n] = -acc;
+  }
+  r[5] = -(d6[1][5] * ix[1] - d6[2][5] * ix[2]);
+  r[6] = -(d6[2][6] * ix[2] - d6[0][5] * ix[0]);
+  r[7] = -(d6[0][6] * ix[0] - d6[1][6] * ix[1]);
+  rk_apply<STAGE>(a, c, r);
+}
+
 template <typename TS>
 void launch_update(int stage, const UpdArgs<TS>& a, bool ho, hipStream_t s) {
   const dim3 grid = tile_grid<kBlockY, 1>(a.g);
@@ -994,7 +1054,15 @@ void launch_update(int stage, const UpdArgs<TS>& a, bool ho, hipStream_t s) {
   } else if (a.g.nz < 4) {
     SRMHD_UPD(k_update_ho, TS, true)
   } else {
-    SRMHD_UPD(k_update_ho, TS, false)
+    const dim3 grid3 = tile_grid<4, 4>(a.g);
+    const dim3 blk3 = tile_block<4, 4>();
+    switch (stage) {
+      case 0: hipLaunchKernelGGL((k_update_ho3<0, TS>), grid3, blk3, 0, s, a); break;
+      case 1: hipLaunchKernelGGL((k_update_ho3<1, TS>), grid3, blk3, 0, s, a); break;
+      case 2: hipLaunchKernelGGL((k_update_ho3<2, TS>), grid3, blk3, 0, s, a); break;
+      case 3: hipLaunchKernelGGL((k_update_ho3<3, TS>), grid3, blk3, 0, s, a); break;
+      default: hipLaunchKernelGGL((k_update_ho3<4, TS>), grid3, blk3, 0, s, a); break;
+    }
   }
 #undef SRMHD_UPD
 }
