@@ -184,7 +184,8 @@ def test_mixed_ho_close_to_fp64_ho():
 
 @pytest.mark.parametrize("shape,kw,okw", [((2, 3, 20), dict(), dict()),
                                           ((1, 5, 70), dict(high_order=True), dict(ho=1)),
-                                          ((3, 1, 9), dict(recon="mc"), dict(recon=1))])
+                                          ((3, 1, 9), dict(recon="mc"), dict(recon=1)),
+                                          ((9, 2, 20), dict(high_order=True), dict(ho=1))])
 def test_rhs_thin_boxes(shape, kw, okw):
     """Directions with fewer than 4 cells (stencils that wrap more than once)
     on rough random states, against the oracle element by element."""
