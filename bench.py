@@ -12,6 +12,10 @@ Prints one JSON line.  Besides the contract keys it carries:
                    algorithmic bytes and flops per launch over its average
                    duration from HIP events recorded on the library's stream
                    during a second, instrumented run of the same steps;
+  stream_copy_gbs, hbm_roofline_frac_step_vs_copy
+                -- the measured bandwidth of a plain 2 GiB device copy, and the
+                   step-level HBM fraction (state bytes per cell-step x rate)
+                   against it as well as against the 8 TB/s peak;
   cpu_baseline  -- the FP64 CPU oracle timed on this host on a bounded sample
                    (the same wave at 64^3, a few steps, all cores; then one
                    thread);
@@ -109,6 +113,29 @@ def profiled_traffic(kernel_cls):
         if all(k in got for k, _ in parts):
             return int(sum(got[k] * w for k, w in parts) / sum(w for _, w in parts))
     return None
+
+
+def stream_copy_gbs(gib=2, reps=5):
+    """Measured HBM bandwidth of a plain device copy of `gib` GiB (read +
+    write bytes over the average of `reps` copies, HIP events): the practical
+    ceiling the step-level fraction is also quoted against."""
+    import torch
+    nb = gib * (1 << 30)
+    src = torch.ones(nb // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2.0 * nb / (ms / 1e3) / 1e9
 
 
 def run_form(n, precision, steps, warmup, mlp=None, **scheme):
@@ -365,6 +392,8 @@ def main():
                      "alu_tflops": round(tfl, 3), "hbm_gbs": round(gbs, 1)})
         print(f"[bench] kernel timing: {json.dumps(kernels)}", file=sys.stderr, flush=True)
     S.close()
+    copy_gbs = stream_copy_gbs()
+    print(f"[bench] plain device copy: {copy_gbs:.0f} GB/s", file=sys.stderr, flush=True)
 
     forms = None
     if not args.no_forms:
@@ -417,6 +446,8 @@ def main():
                    "cells": n ** 3, "precision": args.precision, "guess": args.guess,
                    "newton_stats": bool(args.stats)},
         "hbm_roofline_frac_step": round(value * 1e6 * step_bytes / (HBM_PEAK_GBS * 1e9), 4),
+        "stream_copy_gbs": round(copy_gbs, 1),
+        "hbm_roofline_frac_step_vs_copy": round(value * 1e6 * step_bytes / (copy_gbs * 1e9), 4),
         "roofline": roof,
         "cpu_baseline": cpu,
         "kernels": kernels,
