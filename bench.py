@@ -188,6 +188,17 @@ def run_form(n, precision, steps, warmup, mlp=None, **scheme):
             "kernel_ms": {k: round(t / c, 4) for k, (t, c) in kt.items() if c}}
 
 
+def workload_label(n, precision="fp64", high_order=False, recon="mp5", time_order=3,
+                   guess="prev"):
+    """config.workload of the timed run: what the timed steps compute."""
+    scheme = ("point-value MP5, sixth-order INT/DER (HO)" if high_order else
+              ("MP5" if recon == "mp5" else "linear MC"))
+    prec = "FP64" if precision == "fp64" else "FP64 state, FP32 REC and face fluxes"
+    g = {"prev": "previous-W", "mlp": "learned", "cold": "cold"}[guess]
+    return (f"CPA Alfven wave on the box diagonal, {n}^3, {prec}, {scheme} + HLL + UCT + "
+            f"SSP-RK{time_order}, CFL 0.5, {g} Newton guess")
+
+
 def cpu_baseline(seconds_target=15.0):
     """The oracle (as it stands) on the same wave at 64^3, on all host cores,
     then on one thread."""
@@ -210,11 +221,21 @@ def cpu_baseline(seconds_target=15.0):
         return n ** 3 * nsteps / el / 1e6, nsteps, el
 
     cores = oracle.num_threads()
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     v, nsteps, el = rate(8)
     oracle.set_num_threads(1)
     v1, nsteps1, el1 = rate(3)
     oracle.set_num_threads(cores)
-    return {"value": v, "unit": "Mcell-updates/s", "cores": cores, "kind": "oracle",
+    return {"value": v, "unit": "Mcell-updates/s", "cores": cores, "cpu_model": model,
+            "kind": "oracle",
             "sample": f"diagonal CPA {n}^3, {nsteps} RK3 steps after 1 warm-up step, FP64, "
                       f"OpenMP over z ({el:.1f} s)",
             "single_thread_value": v1,
@@ -279,7 +300,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--stats", action="store_true", help="collect Newton statistics while timed")
     ap.add_argument("--high-order", action="store_true",
@@ -322,10 +343,10 @@ def main():
         del src, dst
 
     n = args.n
+    workload = workload_label(n, args.precision, args.high_order, args.recon, args.time_order,
+                              args.guess)
     print(f"[bench] building the {n}^3 diagonal CPA", file=sys.stderr, flush=True)
     prim5, bf, _ = inputs.cpa(n, diagonal=True, device="cuda")
-    scheme = ("point-value MP5, sixth-order INT/DER" if args.high_order else
-              ("MP5" if args.recon == "mp5" else "linear MC"))
     step_bytes = STEP_BYTES if args.time_order == 3 else STEP_BYTES_RK2
     S = Solver(n, precision=args.precision, collect_stats=args.stats, recon=args.recon,
                time_order=args.time_order, high_order=args.high_order)
@@ -341,15 +362,20 @@ def main():
     torch.cuda.synchronize()
     print(f"[bench] warm-up done ({args.warmup} steps)", file=sys.stderr, flush=True)
 
+    # the timed region: K steps between HIP events on the library's stream,
+    # three times; the median run is the value
     stream = S.stream
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    S.step(args.steps)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
+    runs = []
+    for _ in range(3):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        S.step(args.steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        runs.append(e0.elapsed_time(e1))
+    ms = sorted(runs)[1]
     ms_per_step = ms / args.steps
     value = n ** 3 * args.steps / (ms / 1e3) / 1e6
     diag = S.diagnostics()
@@ -405,11 +431,12 @@ def main():
         # the paper's two other configurations: HO = YES (with UCT), and
         # second-order time stepping with linear reconstruction
         for prec in ("fp64", "mixed"):
-            for key, scheme in (("ho", dict(high_order=True)),
-                                ("mc+rk2", dict(recon="mc", time_order=2))):
+            for key, form_scheme in (("ho", dict(high_order=True)),
+                                     ("mc+rk2", dict(recon="mc", time_order=2))):
                 name = f"{prec}+{key}"
                 print(f"[bench] form {name} at {args.forms_n}^3", file=sys.stderr, flush=True)
-                forms[name] = run_form(args.forms_n, prec, max(5, args.steps // 2), 2, **scheme)
+                forms[name] = run_form(args.forms_n, prec, max(5, args.steps // 2), 2,
+                                       **form_scheme)
         print("[bench] training the learned guess", file=sys.stderr, flush=True)
         t0 = time.perf_counter()
         mlp, hist, npairs = train_default()
@@ -436,13 +463,13 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 4),
+        "ms_per_step_runs": [round(r / args.steps, 4) for r in runs],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f64 state + f32 REC/flux",
         "data": "synthetic",
-        "config": {"workload": f"CPA Alfven wave on the box diagonal, {n}^3, FP64 state, "
-                               f"{scheme} + HLL + UCT + SSP-RK{args.time_order}, CFL 0.5",
+        "config": {"workload": workload,
                    "cells": n ** 3, "precision": args.precision, "guess": args.guess,
                    "newton_stats": bool(args.stats)},
         "hbm_roofline_frac_step": round(value * 1e6 * step_bytes / (HBM_PEAK_GBS * 1e9), 4),

@@ -171,10 +171,33 @@ int srmhd_get_diagnostics(srmhd_ctx *ctx, srmhd_diag *out);
 int srmhd_reset_counters(srmhd_ctx *ctx);
 
 /* Simulated time and step count (host values).  get syncs; set is
- * asynchronous.  With the caller-owned state arrays these make a
- * checkpoint. */
+ * asynchronous. */
 int srmhd_get_time(srmhd_ctx *ctx, double *t, long *step, double *dt);
 int srmhd_set_time(srmhd_ctx *ctx, double t, long step);
+
+/* The evolved state of the scheme (Sec. 3): the cell-centred conserved
+ * variables D, S, U, the staggered face B, and the per-cell Newton guess W
+ * (the previous inversion's converged W = rho h Gamma^2), with the simulated
+ * time and step count.  Together they are a checkpoint: a context given them
+ * by srmhd_set_state continues bit for bit as the one they came from.
+ *
+ * srmhd_get_state copies the state into caller device arrays (cons[5],
+ * bface[3], w; each nx*ny*nz doubles, the layout above; cons, bface or w may
+ * be NULL to skip) and the time and step count into host values (t, step;
+ * either may be NULL).  Syncs.  SRMHD_E_STATE before the state is set.
+ *
+ * srmhd_set_state copies cons[5] and bface[3] (device, required) into the
+ * context's state and w (device) into its guess array; w = NULL means no
+ * previous W: the next inversion starts from the learned guess (learned
+ * form) or from U.  Sets t and the step count, clears the counters, the
+ * running speed maximum and the error word.  The face B should be
+ * divergence-free as the scheme keeps it; it is not checked.  Source arrays
+ * may be the context's own (no copy).  Asynchronous. */
+int srmhd_get_state(srmhd_ctx *ctx, double *const cons[5], double *const bface[3],
+                    double *w, double *t, long *step);
+int srmhd_set_state(srmhd_ctx *ctx, const double *const cons[5],
+                    const double *const bface[3], const double *w, double t,
+                    long step);
 
 /* Per-kernel timing with HIP events recorded on the context's stream around
  * every launch (adds a small host/queue overhead per launch; off by
@@ -222,6 +245,16 @@ int srmhd_set_mlp(srmhd_ctx *ctx, const float *params, const uint16_t *w_bf16,
 /* Switch the Newton guess (SRMHD_GUESS_*; _MLP needs srmhd_set_mlp). */
 int srmhd_set_guess(srmhd_ctx *ctx, int guess);
 
+/* The learned guess of every cell of the current state, from the same
+ * feature and inference code the learned-guess inversion runs (nothing is
+ * inverted; the state and W are not modified).  out (device, 2*nx*ny*nz
+ * floats): the network's de-standardised outputs, log(p/D) at out[id] and
+ * log Gamma at out[ncell + id]; w0 (device, nx*ny*nz doubles, or NULL): the
+ * guess W0 = D Gamma + g/(g-1) p Gamma^2 they give (with log Gamma clamped
+ * at 0), or -1 where a feature is not finite.  Needs srmhd_set_mlp
+ * (SRMHD_E_STATE otherwise).  Asynchronous. */
+int srmhd_mlp_guess(srmhd_ctx *ctx, float *out, double *w0);
+
 /* Training pairs from the current state: each cell is kept with probability
  * frac (counter-based hash of its index and seed), inverted from the stored W
  * (W not modified); feats (device, cap x 5) get its features, targets
@@ -257,6 +290,11 @@ int srmhd_mlp_backward(const uint16_t *w_bf16, void *cache, float *grad, int bat
 int srmhd_mlp_adam(float *params, uint16_t *w_bf16, float *m, float *v,
                    const float *grad, int n, float lr, float beta1, float beta2,
                    float eps, int t, void *stream);
+
+/* Identifier of the sources the library was built from (sha256 prefix over
+ * the HIP sources and this header, fixed at build time); a binding compares
+ * it with the sources beside it to refuse a stale build. */
+const char *srmhd_build_id(void);
 
 /* Message of the last failure on ctx (NULL ctx: last creation failure). */
 const char *srmhd_last_error(const srmhd_ctx *ctx);

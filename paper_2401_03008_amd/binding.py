@@ -70,8 +70,22 @@ _VP = C.c_void_p
 _CTX = C.c_void_p
 
 
+def check_build_id(L, root=None):
+    """Raise unless the library L was built from the sources under root (the
+    repository this binding sits in by default)."""
+    from .build import ROOT, source_id
+    want = source_id(root or ROOT)
+    L.srmhd_build_id.restype = C.c_char_p
+    got = (L.srmhd_build_id() or b"").decode()
+    if got != want:
+        raise RuntimeError(
+            f"{LIB_PATH} was built from other sources (build id {got}, sources {want}): "
+            "rebuild it (python -c 'import __graft_entry__ as g; g.build()')")
+
+
 def lib():
-    """Load libsrmhd.so (built by ``paper_2401_03008_amd.build``)."""
+    """Load libsrmhd.so (built by ``paper_2401_03008_amd.build``); refuses a
+    library built from sources other than those beside it."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
@@ -79,6 +93,7 @@ def lib():
                 f"{LIB_PATH} is missing: build the HIP library first "
                 "(python -c 'import __graft_entry__ as g; g.build()')")
         L = C.CDLL(LIB_PATH)
+        check_build_id(L)
         L.srmhd_config_default.argtypes = [C.POINTER(Config)]
         L.srmhd_work_bytes.argtypes = [C.POINTER(Config), C.POINTER(C.c_size_t)]
         L.srmhd_create.argtypes = [C.POINTER(Config), C.POINTER(Buffers), _VP, C.POINTER(_CTX)]
@@ -91,6 +106,11 @@ def lib():
         L.srmhd_get_time.argtypes = [_CTX, C.POINTER(C.c_double), C.POINTER(C.c_long),
                                      C.POINTER(C.c_double)]
         L.srmhd_set_time.argtypes = [_CTX, C.c_double, C.c_long]
+        L.srmhd_get_state.argtypes = [_CTX, C.POINTER(_VP), C.POINTER(_VP), _VP,
+                                      C.POINTER(C.c_double), C.POINTER(C.c_long)]
+        L.srmhd_set_state.argtypes = [_CTX, C.POINTER(_VP), C.POINTER(_VP), _VP, C.c_double,
+                                      C.c_long]
+        L.srmhd_mlp_guess.argtypes = [_CTX, _VP, _VP]
         L.srmhd_set_mlp.argtypes = [_CTX, _VP, _VP, C.POINTER(C.c_float)]
         L.srmhd_set_guess.argtypes = [_CTX, C.c_int]
         L.srmhd_harvest.argtypes = [_CTX, _VP, _VP, C.c_int, C.c_double, C.c_uint,
@@ -196,6 +216,31 @@ def srmhd_get_time(ctx):
 
 def srmhd_set_time(ctx, t, step):
     _check(lib().srmhd_set_time(ctx, float(t), int(step)), ctx)
+
+
+def srmhd_get_state(ctx, cons, bface, w):
+    """cons (5 device pointers or None), bface (3 or None), w (pointer or 0);
+    returns (t, step)."""
+    t, st = C.c_double(), C.c_long()
+    pc = _ptrs(cons, 5) if cons is not None else None
+    pb = _ptrs(bface, 3) if bface is not None else None
+    _check(lib().srmhd_get_state(ctx, pc, pb, _VP(int(w) or None), C.byref(t), C.byref(st)),
+           ctx)
+    return t.value, st.value
+
+
+def srmhd_set_state(ctx, cons, bface, w, t, step):
+    """w: device pointer, or 0/None for no previous W."""
+    _check(lib().srmhd_set_state(ctx, _ptrs(cons, 5), _ptrs(bface, 3), _VP(int(w or 0) or None),
+                                 float(t), int(step)), ctx)
+
+
+def srmhd_mlp_guess(ctx, out, w0=0):
+    _check(lib().srmhd_mlp_guess(ctx, _VP(int(out)), _VP(int(w0 or 0) or None)), ctx)
+
+
+def srmhd_build_id():
+    return (lib().srmhd_build_id() or b"").decode()
 
 
 MLP_NPARAM = 4674

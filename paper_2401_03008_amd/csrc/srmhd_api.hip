@@ -49,6 +49,10 @@ struct srmhd_ctx {
 
 static std::string g_create_error;
 
+#ifndef SRMHD_BUILD_ID
+#define SRMHD_BUILD_ID "unknown"
+#endif
+
 namespace {
 
 int fail(srmhd_ctx* c, int code, const std::string& msg) {
@@ -103,7 +107,11 @@ std::string validate(const srmhd_config* c) {
   if (!c) return "config is NULL";
   if (c->nx < 1 || c->ny < 1 || c->nz < 1) return "nx, ny, nz must each be >= 1";
   if ((long long)c->nx * c->ny * c->nz >= (1LL << 31)) return "nx*ny*nz must be < 2^31";
-  if (c->nz > 65535 || (c->ny + kBlockY - 1) / kBlockY > 65535) return "grid too tall";
+  // every launch is a 1D grid of tiles (at most 64 x 8 x 8 cells, tile rows
+  // padded to groups of 8): its thread count must stay below 2^32
+  if ((double)(c->nx + 63) * (c->ny + 8) * (c->nz + 8) + 32768.0 * ((c->nx + 63) / 64) >=
+      4294967295.0)
+    return "box too large for one launch grid";
   if (!(c->lx > 0 && c->ly > 0 && c->lz > 0)) return "box lengths must be > 0";
   if (!(c->gamma_ad > 1.0 && c->gamma_ad <= 2.0)) return "gamma_ad must be in (1, 2]";
   if (!(c->dt_fixed > 0.0) && !(c->cfl > 0.0 && c->cfl <= 1.0))
@@ -255,8 +263,18 @@ void launch_c2p_into(srmhd_ctx* c, const StageState& st, double* const* prim64,
   a.mlp = c->mlp;
   a.counters = c->counters;
   a.err = &c->sc->err;
+  a.mlp_out = nullptr;
+  a.mlp_w0 = nullptr;
   KTimer kt(c, 0);
   launch_c2p(a, c->cfg.collect_stats != 0, c->stream);
+}
+
+// Device-to-device copy of one grid array on the context's stream (nothing
+// to do when source and destination are the same array).
+int copy_grid(srmhd_ctx* c, double* dst, const double* src, const char* what) {
+  if (dst == src) return SRMHD_OK;
+  return hip_check(c, hipMemcpyAsync(dst, src, (size_t)c->ncell * sizeof(double),
+                                     hipMemcpyDeviceToDevice, c->stream), what);
 }
 
 // One RK stage (1..3 of SSP-RK3; 1 and 4 of SSP-RK2), or stage 0 = L(U)
@@ -471,6 +489,94 @@ int srmhd_get_primitives(srmhd_ctx* c, double* const prim[8]) {
   launch_c2p_into(c, stage_state(c, 0), prim, nullptr, guess_code(c));
   return check_launch(c, "get_primitives");
 }
+
+int srmhd_get_state(srmhd_ctx* c, double* const cons[5], double* const bface[3], double* w,
+                    double* t, long* step) {
+  if (!c) return SRMHD_E_INVAL;
+  if (!c->initialized) return fail(c, SRMHD_E_STATE, "get_state before the state is set");
+  if (cons)
+    for (int n = 0; n < 5; ++n)
+      if (!cons[n]) return fail(c, SRMHD_E_INVAL, "cons entry is NULL");
+  if (bface)
+    for (int d = 0; d < 3; ++d)
+      if (!bface[d]) return fail(c, SRMHD_E_INVAL, "bface entry is NULL");
+  int rc = SRMHD_OK;
+  for (int n = 0; cons && n < 5 && rc == SRMHD_OK; ++n)
+    rc = copy_grid(c, cons[n], c->buf.cons[n], "get_state copy");
+  for (int d = 0; bface && d < 3 && rc == SRMHD_OK; ++d)
+    rc = copy_grid(c, bface[d], c->buf.bface[d], "get_state copy");
+  if (rc == SRMHD_OK && w) rc = copy_grid(c, w, c->buf.guess_w, "get_state copy");
+  if (rc != SRMHD_OK) return rc;
+  double tt = 0.0, dt = 0.0;
+  long st = 0;
+  rc = srmhd_get_time(c, &tt, &st, &dt);  // syncs: the copies are complete
+  if (rc != SRMHD_OK) return rc;
+  if (t) *t = tt;
+  if (step) *step = st;
+  return SRMHD_OK;
+}
+
+int srmhd_set_state(srmhd_ctx* c, const double* const cons[5], const double* const bface[3],
+                    const double* w, double t, long step) {
+  if (!c) return SRMHD_E_INVAL;
+  if (!cons || !bface) return fail(c, SRMHD_E_INVAL, "cons/bface is NULL");
+  for (int n = 0; n < 5; ++n)
+    if (!cons[n]) return fail(c, SRMHD_E_INVAL, "cons entry is NULL");
+  for (int d = 0; d < 3; ++d)
+    if (!bface[d]) return fail(c, SRMHD_E_INVAL, "bface entry is NULL");
+  if (!std::isfinite(t) || step < 0) return fail(c, SRMHD_E_INVAL, "bad time or step");
+  int rc = SRMHD_OK;
+  for (int n = 0; n < 5 && rc == SRMHD_OK; ++n)
+    rc = copy_grid(c, c->buf.cons[n], cons[n], "set_state copy");
+  for (int d = 0; d < 3 && rc == SRMHD_OK; ++d)
+    rc = copy_grid(c, c->buf.bface[d], bface[d], "set_state copy");
+  if (rc != SRMHD_OK) return rc;
+  if (w) {
+    rc = copy_grid(c, c->buf.guess_w, w, "set_state copy");
+    if (rc != SRMHD_OK) return rc;
+  } else {
+    // no previous W: every guess is unusable, so the next inversion starts
+    // from the learned guess (learned form) or from U
+    launch_fill_f64(c->buf.guess_w, (size_t)c->ncell, -1.0, c->stream);
+  }
+  // scalars (running max, dt, error word) and counters start afresh
+  const Layout L = layout_of(&c->cfg);
+  launch_zero_u64((unsigned long long*)c->buf.work, L.off_part / sizeof(unsigned long long),
+                  c->stream);
+  launch_set_time(c->sc, t, step, c->stream);
+  rc = check_launch(c, "set_state");
+  if (rc == SRMHD_OK) c->initialized = true;
+  return rc;
+}
+
+int srmhd_mlp_guess(srmhd_ctx* c, float* out, double* w0) {
+  if (!c) return SRMHD_E_INVAL;
+  if (!c->initialized) return fail(c, SRMHD_E_STATE, "mlp_guess before the state is set");
+  if (!c->mlp_set) return fail(c, SRMHD_E_STATE, "mlp_guess needs srmhd_set_mlp first");
+  if (!out) return fail(c, SRMHD_E_INVAL, "out is NULL");
+  C2PArgs a;
+  std::memset(&a, 0, sizeof(a));
+  const StageState st = stage_state(c, 0);
+  a.g = c->g;
+  for (int n = 0; n < 5; ++n) a.cons[n] = st.cons[n];
+  for (int d = 0; d < 3; ++d) a.bf[d] = st.bf[d];
+  a.W = c->buf.guess_w;
+  a.gam = c->cfg.gamma_ad;
+  a.tol = c->cfg.newton_tol;
+  a.pfloor = c->cfg.pfloor;
+  a.maxit = c->cfg.newton_maxit;
+  a.guess = 1;
+  a.ho = c->cfg.high_order;
+  a.mlp = c->mlp;
+  a.counters = c->counters;
+  a.err = &c->sc->err;
+  a.mlp_out = out;
+  a.mlp_w0 = w0;
+  launch_c2p(a, false, c->stream);
+  return check_launch(c, "mlp_guess");
+}
+
+const char* srmhd_build_id(void) { return SRMHD_BUILD_ID; }
 
 int srmhd_get_diagnostics(srmhd_ctx* c, srmhd_diag* out) {
   if (!c) return SRMHD_E_INVAL;

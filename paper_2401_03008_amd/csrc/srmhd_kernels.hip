@@ -372,7 +372,9 @@ __device__ int con2prim(const double* u, double bx, double by, double bz, double
 // learned guess (mode 1): the network's (log(p/D), log Gamma) gives
 // W0 = D Gamma + g/(g-1) p Gamma^2; if Newton from W0 does not converge, or W0
 // is unusable, the inversion is redone from the previous W and counted.
-template <bool STATS, bool MLP>
+// PROBE (with MLP): write the network outputs and W0 of every cell and stop
+// before Newton (the same feature and inference code as the inversion).
+template <bool STATS, bool MLP, bool PROBE = false>
 __global__ __launch_bounds__(kThreads) void k_c2p(C2PArgs a) {
   __shared__ unsigned s_cnt[CNT_N];
   __shared__ __align__(16) uint16_t s_lx[MLP ? kBlockY * 64 * 16 : 4];
@@ -408,6 +410,15 @@ __global__ __launch_bounds__(kThreads) void k_c2p(C2PArgs a) {
     const double lor = (double)__expf(fmaxf(out[1], 0.f));
     const double pg = u[0] * (double)__expf(out[0]);
     W = fin ? u[0] * lor + a.gam / (a.gam - 1.0) * pg * lor * lor : -1.0;
+    if constexpr (PROBE) {
+      if (c.valid) {
+        const long long nc = (long long)a.g.nx * a.g.ny * a.g.nz;
+        a.mlp_out[c.id] = out[0];
+        a.mlp_out[nc + c.id] = out[1];
+        if (a.mlp_w0) a.mlp_w0[c.id] = W;
+      }
+      return;
+    }
     if (c.valid) {
       rc = con2prim(u, b[0], b[1], b[2], a.gam, W, a.maxit, a.tol, a.pfloor, pr, iters, floored,
                     true);
@@ -452,6 +463,10 @@ void launch_c2p(const C2PArgs& a, bool stats, hipStream_t s) {
   const dim3 grid = cell_grid(a.g);
   dim3 blk(kBlockX, kBlockY);
   const bool mlp = a.guess == 1;
+  if (mlp && a.mlp_out) {
+    hipLaunchKernelGGL((k_c2p<false, true, true>), grid, blk, 0, s, a);
+    return;
+  }
   if (stats) {
     if (mlp) hipLaunchKernelGGL((k_c2p<true, true>), grid, blk, 0, s, a);
     else hipLaunchKernelGGL((k_c2p<true, false>), grid, blk, 0, s, a);
@@ -1096,6 +1111,16 @@ __global__ void k_zero_u64(unsigned long long* p, size_t n) {
 void launch_zero_u64(unsigned long long* p, size_t n, hipStream_t s) {
   if (n == 0) return;
   hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+}
+
+__global__ void k_fill_f64(double* p, size_t n, double v) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+void launch_fill_f64(double* p, size_t n, double v, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
 }
 
 __global__ void k_set_time(DevScalars* sc, double t, long long step) {

@@ -63,6 +63,13 @@ struct C2PArgs {
   MlpDev mlp;
   unsigned long long* counters;
   unsigned int* err;
+  // Learned-guess probe (guess 1 only): when mlp_out is set the kernel writes
+  // the network's de-standardised outputs (log(p/D), log Gamma) of every cell
+  // to mlp_out[0..ncell) and mlp_out[ncell..2 ncell), and the guess W0 they
+  // give (-1 where the features are not finite) to mlp_w0 if set, and stops
+  // there: no Newton, no W, no primitives.
+  float* mlp_out;
+  double* mlp_w0;
 };
 
 struct HarvestArgs {
@@ -158,6 +165,7 @@ template <typename TS>
 void launch_update(int stage, const UpdArgs<TS>& a, bool ho, hipStream_t s);
 void launch_dt(DevScalars* sc, double cfl, double dt_fixed, hipStream_t s);
 void launch_zero_u64(unsigned long long* p, size_t n, hipStream_t s);
+void launch_fill_f64(double* p, size_t n, double v, hipStream_t s);
 void launch_set_time(DevScalars* sc, double t, long long step, hipStream_t s);
 void launch_reduce(const ReduceArgs& a, hipStream_t s);
 int reduce_blocks(const GridDims& g);

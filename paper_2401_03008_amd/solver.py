@@ -3,8 +3,8 @@
 PyTorch supplies device memory and the stream; every step of the solver runs
 in libsrmhd's HIP kernels.  State tensors (float64, shape (n, nz, ny, nx)):
 ``cons`` = D, Sx, Sy, Sz, U; ``bface`` = face B_x, B_y, B_z; ``W`` = Newton
-guess.  They are the caller-owned buffers of the C ABI, so copying them (plus
-``time()``) is a checkpoint.
+guess: the caller-owned buffers of the C ABI.  ``checkpoint``/``restore`` go
+through srmhd_get_state / srmhd_set_state.
 """
 from __future__ import annotations
 
@@ -131,13 +131,35 @@ class Solver:
     def set_time(self, t, step):
         B.srmhd_set_time(self.ctx, t, step)
 
+    def get_state(self):
+        """The state through srmhd_get_state: new tensors cons (5, ...),
+        bface (3, ...), W, and host t, step."""
+        cons = torch.empty_like(self.cons)
+        bface = torch.empty_like(self.bface)
+        W = torch.empty_like(self.W)
+        t, st = B.srmhd_get_state(self.ctx, [a.data_ptr() for a in cons],
+                                  [b.data_ptr() for b in bface], W.data_ptr())
+        return {"cons": cons, "bface": bface, "W": W, "t": t, "step": st}
+
+    def set_state(self, cons, bface, W=None, t=0.0, step=0):
+        """srmhd_set_state from device tensors (W None: no previous W)."""
+        c = [self._dev(a) for a in cons]
+        b = [self._dev(a) for a in bface]
+        w = self._dev(W) if W is not None else None
+        B.srmhd_set_state(self.ctx, [a.data_ptr() for a in c], [a.data_ptr() for a in b],
+                          w.data_ptr() if w is not None else 0, t, step)
+        self.stream.synchronize()  # inputs may be temporaries
+
     def checkpoint(self):
-        t, st, dt = self.time()
-        return {"cons": self.cons.clone(), "bface": self.bface.clone(), "W": self.W.clone(),
-                "t": t, "step": st}
+        return self.get_state()
 
     def restore(self, ck):
-        self.cons.copy_(ck["cons"])
-        self.bface.copy_(ck["bface"])
-        self.W.copy_(ck["W"])
-        self.set_time(ck["t"], ck["step"])
+        self.set_state(ck["cons"], ck["bface"], ck["W"], ck["t"], ck["step"])
+
+    def mlp_guess(self):
+        """(out (2, ...) float32: log(p/D), log Gamma; W0 (...) float64) of
+        the learned guess on the current state (srmhd_mlp_guess)."""
+        out = torch.empty((2,) + self.shape, dtype=torch.float32, device=self.device)
+        w0 = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+        B.srmhd_mlp_guess(self.ctx, out.data_ptr(), w0.data_ptr())
+        return out, w0

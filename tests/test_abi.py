@@ -87,3 +87,31 @@ def test_binding_fails_loudly_without_library(monkeypatch):
     monkeypatch.setattr(B, "LIB_PATH", "/nonexistent/libsrmhd.so")
     with pytest.raises(RuntimeError, match="missing"):
         B.lib()
+
+
+def test_null_state_calls(L):
+    assert L.srmhd_get_state(None, None, None, None, None, None) == B.SRMHD_E_INVAL
+    assert L.srmhd_set_state(None, None, None, None, 0.0, 0) == B.SRMHD_E_INVAL
+    assert L.srmhd_mlp_guess(None, None, None) == B.SRMHD_E_INVAL
+
+
+def test_library_matches_its_sources(L):
+    from paper_2401_03008_amd.build import source_id
+    assert B.srmhd_build_id() == source_id()
+
+
+def test_stale_library_rejected(L, tmp_path):
+    """A library whose build id differs from the sources beside it is refused:
+    a copy of the sources with one kernel file edited gives another id."""
+    import shutil
+    from paper_2401_03008_amd.build import ROOT, source_files, source_id
+    for f in source_files(ROOT):
+        rel = os.path.relpath(f, ROOT)
+        os.makedirs(tmp_path / os.path.dirname(rel), exist_ok=True)
+        shutil.copy(f, tmp_path / rel)
+    B.check_build_id(L, str(tmp_path))  # identical copy: accepted
+    k = tmp_path / "paper_2401_03008_amd" / "csrc" / "srmhd_kernels.hip"
+    k.write_text(k.read_text() + "\n// edited\n")
+    assert source_id(str(tmp_path)) != source_id()
+    with pytest.raises(RuntimeError, match="other sources"):
+        B.check_build_id(L, str(tmp_path))

@@ -24,3 +24,18 @@ def test_kernel_units_and_profile_lookup():
         assert b64 > bmx > 0 and fl > 0
         t = bench.profiled_traffic(cls)
         assert t is None or t > 0.5 * b64 * 256 ** 3
+
+
+def test_workload_label_names_the_timed_scheme():
+    sys.path.insert(0, ROOT)
+    import bench
+    lab = bench.workload_label(512)
+    assert "512^3" in lab and "MP5" in lab and "SSP-RK3" in lab and "FP64" in lab
+    assert "MC" not in lab and "HO" not in lab
+    lab = bench.workload_label(256, "mixed", recon="mc", time_order=2)
+    assert "linear MC" in lab and "SSP-RK2" in lab and "FP32" in lab
+    assert "HO" in bench.workload_label(512, high_order=True)
+    # the default run is the 512^3 plain FP64 wave
+    import argparse  # noqa: F401
+    src = open(os.path.join(ROOT, "bench.py")).read()
+    assert 'ap.add_argument("--n", type=int, default=512)' in src

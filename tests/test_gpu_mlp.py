@@ -245,3 +245,55 @@ def test_turbulence_run_driver_small():
     print("[gpu] mixed+learned vs fp64 (64^3 turbulence, 20 steps):", ["%.1e" % d for d in diff],
           "newton", a["newton"], b["newton"], flush=True)
     assert max(diff) < 1e-4
+
+
+def test_in_kernel_guess_matches_reference():
+    """The learned guess as the inversion kernel computes it (srmhd_mlp_guess:
+    the same feature and in-wavefront MFMA inference code) against the FP64
+    reference network on the same BF16-rounded weights, on a ragged
+    turbulence box (x rows shorter than a wavefront, partial tiles in y).
+    Features come from the oracle's inversion inputs (conserved D, S, U and
+    centred B), standardised with the network's normalisation."""
+    from paper_2401_03008_amd.solver import Solver
+    nx, ny, nz = 40, 10, 7
+    prim5, bf = I.turbulence((nx, ny, nz), sigma0=3.0, gamma_max=3.0)
+    mlp = _mlp(6)
+    g = O.Grid(nx, ny, nz)
+    cons, W = g.init(prim5, bf)
+    prim, _, nf = g.c2p(cons, bf, W)
+    assert nf == 0
+    D, U = cons[0].ravel(), cons[4].ravel()
+    S3 = np.stack([c.ravel() for c in cons[1:4]], 1)
+    B3 = np.stack([prim[5 + d].ravel() for d in range(3)], 1)
+    fr = M.features(D, S3, U, B3)
+    mlp.norm = [*fr.mean(0), *fr.std(0), -1.0, 0.2, 0.5, 0.3]
+    S = Solver(nx, ny, nz)
+    S.init(prim5, bf)
+    S.set_mlp(mlp)
+    W_before = S.W.clone()
+    out, w0 = S.mlp_guess()
+    torch.cuda.synchronize()
+    assert torch.equal(S.W, W_before)  # the probe leaves the state's W alone
+    out = out.double().cpu().numpy().reshape(2, -1).T
+    w0 = w0.cpu().numpy().ravel()
+    S.close()
+    nrm = np.array(mlp.norm)
+    xr = (fr - nrm[0:5]) / nrm[5:10]
+    th = _ref_theta(mlp)
+    yr, _ = M.forward(th, M.bf16_round(xr))
+    ref = yr * nrm[12:14] + nrm[10:12]
+    assert out.shape == ref.shape == (nx * ny * nz, 2)
+    assert np.isfinite(out).all()
+    assert _rel_l2(out, ref) < 2e-2
+    # with the BF16 rounding of the hidden activations emulated as well
+    p = M.unpack(th)
+    h1 = M.bf16_round(np.maximum(M.bf16_round(xr) @ p["W1"].T + p["b1"], 0))
+    h2 = M.bf16_round(np.maximum(h1 @ p["W2"].T + p["b2"], 0))
+    ye = (h2 @ p["W3"].T + p["b3"]) * nrm[12:14] + nrm[10:12]
+    print(f"[gpu] in-kernel guess: rel L2 {_rel_l2(out, ref):.2e} (FP64), "
+          f"{_rel_l2(out, ye):.2e} (BF16 activations)", flush=True)
+    assert _rel_l2(out, ye) < 5e-3
+    # W0 from the outputs: D Gamma + 4 p Gamma^2 (gamma 4/3), log Gamma >= 0
+    lor = np.exp(np.maximum(out[:, 1], 0.0))
+    pg = D * np.exp(out[:, 0])
+    np.testing.assert_allclose(w0, D * lor + 4.0 * pg * lor * lor, rtol=2e-6)

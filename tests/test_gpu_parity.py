@@ -359,3 +359,80 @@ def test_kernel_timing_counts_launches():
     assert kt["uct_x"][1] == 6 and kt["uct_y"][1] == 6 and kt["uct_z"][1] == 6
     assert all(v[0] > 0 for v in kt.values())
     S.close()
+
+
+# ------------------------------------------------------------ pressure floor
+def test_pressure_floor_matches_oracle():
+    """A ragged rough box with a quarter of its cells at p = 1e-13 rho and a
+    floor of 1e-10 rho: the inversion floors exactly those cells (count equal
+    to the oracle's), their pressure is 1e-10 rho, and every primitive equals
+    the oracle's."""
+    shape = (8, 12, 70)
+    prim5, bf = _rough_state(shape, 31)
+    rng = np.random.default_rng(32)
+    cold = rng.random(shape) < 0.25
+    prim5[4] = np.ascontiguousarray(np.where(cold, 1e-13 * prim5[0], prim5[4]))
+    S = _solver(shape, pfloor=1e-10)
+    S.init(prim5, bf)
+    S.reset_counters()
+    P = _gpu_prims(S)
+    d = S.diagnostics()
+    g = _oracle(shape, pfloor=1e-10)
+    cons, W = g.init(prim5, bf)
+    g.stats = O.Stats()
+    Pr, it, nf = g.c2p(cons, bf, W)
+    assert nf == 0 and d["c2p_failures"] == 0
+    assert d["floors"] == g.stats.floors == int(cold.sum()) > 0
+    np.testing.assert_array_equal(P[4][cold], 1e-10 * P[0][cold])
+    for q in range(8):
+        np.testing.assert_allclose(P[q], Pr[q], rtol=1e-12, atol=1e-12)
+    S.close()
+
+
+# ---------------------------------------------------------- state round trip
+@pytest.mark.parametrize("kw", [{}, {"precision": "mixed"}, {"high_order": True}])
+def test_state_round_trip_bitwise(kw):
+    """2N steps in one context equal, bit for bit, N steps, srmhd_get_state,
+    srmhd_set_state into a fresh context, and N more steps (state, W, t and
+    step count)."""
+    shape = (16, 20, 24)
+    prim5, bf = I.turbulence((24, 20, 16), gamma_max=2.0)
+    A = _solver(shape, **kw)
+    A.init(prim5, bf)
+    A.step(4)
+    ref = A.get_state()
+    A.close()
+    B1 = _solver(shape, **kw)
+    B1.init(prim5, bf)
+    B1.step(2)
+    ck = B1.get_state()
+    B1.close()
+    B2 = _solver(shape, **kw)
+    B2.set_state(ck["cons"], ck["bface"], ck["W"], ck["t"], ck["step"])
+    B2.step(2)
+    got = B2.get_state()
+    assert got["step"] == ref["step"] == 4 and got["t"] == ref["t"]
+    for k in ("cons", "bface", "W"):
+        assert torch.equal(got[k], ref[k]), k
+    B2.close()
+
+
+def test_set_state_without_w_starts_cold():
+    """set_state with no W: the first inversion starts from U (more Newton
+    iterations) and converges to the same primitives."""
+    shape = (8, 8, 16)
+    prim5, bf = _rough_state(shape, 41)
+    A = _solver(shape)
+    A.init(prim5, bf)
+    ck = A.get_state()
+    Pa = _gpu_prims(A)
+    A.reset_counters()
+    A.primitives()
+    warm = A.diagnostics()["newton_iters"]
+    A.set_state(ck["cons"], ck["bface"], None, 0.5, 7)
+    assert A.time()[:2] == (0.5, 7)
+    Pb = _gpu_prims(A)
+    cold = A.diagnostics()["newton_iters"]
+    assert cold > warm
+    np.testing.assert_allclose(Pb, Pa, rtol=1e-12, atol=1e-12)
+    A.close()

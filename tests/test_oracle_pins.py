@@ -641,3 +641,162 @@ def test_rhs_cells_matches_grid_rhs():
     out = g.rhs_cells(prim, bf, cells)
     full = np.stack([r.ravel() for r in rhs], axis=1)[cells]
     assert np.array_equal(out, full)
+
+
+# ------------------------------------------- fast-speed bound in a moving frame
+def test_speeds_boost_along_field():
+    """v parallel to B parallel to d: a boost along B leaves B unchanged, so
+    the comoving field strength is b^2 = B^2 and v_A^2 = B^2/(rho h + B^2).
+    The bound is then the rest-frame speed w (w^2 = c_s^2 + v_A^2 - c_s^2 v_A^2)
+    added relativistically to the flow speed: (v +- w)/(1 +- v w).  Dropping
+    the (v.B)^2 term of b^2 (b^2 = B^2/Gamma^2) breaks this."""
+    for rho, p, v, Bm in [(1.0, 1.0, 0.3, 1.0), (0.1, 0.05, -0.7, 1.0),
+                          (2.0, 0.01, 0.95, 3.0), (1.0, 0.3, 0.5, 10.0)]:
+        rhoh = rho + 4.0 * p
+        cs2 = GAM * p / rhoh
+        va2 = Bm * Bm / (rhoh + Bm * Bm)
+        w = math.sqrt(cs2 + va2 - cs2 * va2)
+        for d in range(3):
+            pr = np.zeros(8)
+            pr[0], pr[4], pr[1 + d], pr[5 + d] = rho, p, v, Bm
+            lm, lp = O.speeds(pr, d, GAM)
+            assert lp == pytest.approx((v + w) / (1 + v * w), rel=1e-13)
+            assert lm == pytest.approx((v - w) / (1 - v * w), rel=1e-13)
+
+
+def _boost_velocity(u_rest, v):
+    """Velocity in the lab of a signal moving with u_rest in the frame that
+    moves with v (relativistic velocity addition)."""
+    v2 = v @ v
+    lor = 1.0 / math.sqrt(1.0 - v2)
+    vu = u_rest @ v
+    return (u_rest / lor + v + (lor / (1.0 + lor)) * vu * v) / (1.0 + vu)
+
+
+def _front_extremes(w, v, d):
+    """Max and min over rest-frame directions n of the d-component of the
+    lab velocity of a front moving with speed w along n, by brute force: a
+    dense sweep of the sphere, then a local refinement of the best points."""
+    from scipy.optimize import minimize
+
+    def comp(x, sign):
+        th, ph = x
+        n = np.array([math.sin(th) * math.cos(ph), math.sin(th) * math.sin(ph), math.cos(th)])
+        return -sign * _boost_velocity(w * n, v)[d]
+
+    th = np.linspace(0.0, math.pi, 61)
+    ph = np.linspace(0.0, 2 * math.pi, 121)
+    out = []
+    for sign in (1.0, -1.0):
+        best = min(((comp((a, b), sign), a, b) for a in th for b in ph))
+        r = minimize(comp, x0=[best[1], best[2]], args=(sign,), method="Nelder-Mead",
+                     options={"xatol": 1e-13, "fatol": 1e-16, "maxiter": 4000})
+        out.append(-sign * r.fun)
+    return out[0], out[1]
+
+
+def test_speeds_boosted_isotropic_front():
+    """The Del Zanna et al. (2003) bound is the lab-frame reach, along d, of
+    a front that moves isotropically with speed w in the fluid rest frame,
+    w^2 = c_s^2 + v_A^2 - c_s^2 v_A^2, with c_s^2 = gam p/(rho h) and
+    v_A^2 = b^2/(rho h + b^2), b^2 the rest-frame field strength.  Checked
+    against an independent construction for random states with v.B != 0:
+    b^2 = B^2 - E^2 (the field invariant, E = -v x B, which has E' = 0 in the
+    rest frame), and the extremes of the boosted front found by brute force
+    over rest-frame directions."""
+    rng = np.random.default_rng(11)
+    for _ in range(12):
+        pr = _random_prims(rng)
+        rho, p = pr[0], pr[4]
+        v, B = pr[1:4], pr[5:8]
+        E = -np.cross(v, B)
+        b2 = B @ B - E @ E
+        rhoh = rho + 4.0 * p
+        cs2 = GAM * p / rhoh
+        va2 = b2 / (rhoh + b2)
+        w = math.sqrt(cs2 + va2 - cs2 * va2)
+        for d in range(3):
+            lm, lp = O.speeds(pr, d, GAM)
+            hi, lo = _front_extremes(w, v, d)
+            assert lp == pytest.approx(hi, abs=1e-9)
+            assert lm == pytest.approx(lo, abs=1e-9)
+
+
+# ------------------------------------------------------------ pressure floor
+def test_pressure_floor_applied_and_counted():
+    """A state whose inversion gives p below pfloor * rho: the pressure is
+    set to pfloor * rho (rho the rest-frame density D/Gamma, not D), counted
+    once, and rho and v stay those of the exact inverse (the floor acts after
+    Newton).  With no floor the same state inverts to its own tiny p."""
+    pfl = 1e-10
+    for rho, v, B in [(1.0, (0.3, 0.0, 0.0), (0.1, 0.0, 0.0)),
+                      (0.5, (0.2, -0.5, 0.4), (0.3, 0.2, -0.1))]:
+        p = 1e-13 * rho
+        pr = np.array([rho, *v, p, *B])
+        u = O.prim2cons(pr, GAM)
+        v2 = float(np.dot(v, v))
+        Wex = (rho + 4 * p) / (1 - v2)
+        rc, out, W, it, fl = O.con2prim(u, Wex, GAM, pfloor=pfl)
+        assert rc == 0 and fl == 1
+        assert out[4] == pfl * out[0]
+        assert out[0] == pytest.approx(rho, rel=1e-12)
+        np.testing.assert_allclose(out[1:4], v, rtol=0, atol=1e-12)
+        # rho, not D = rho Gamma: Gamma > 1 here, so the two floors differ
+        assert abs(out[4] - pfl * u[0]) > 1e-3 * pfl * rho
+        rc0, out0, _, _, fl0 = O.con2prim(u, Wex, GAM)
+        assert rc0 == 0 and fl0 == 0 and out0[4] < pfl * rho
+    # a pressure above the floor is left alone
+    pr = np.array([1.0, 0.1, 0.0, 0.0, 1e-6, 0.1, 0.0, 0.0])
+    rc, out, _, _, fl = O.con2prim(O.prim2cons(pr, GAM), 1.0, GAM, pfloor=pfl)
+    assert rc == 0 and fl == 0 and out[4] == pytest.approx(1e-6, rel=1e-8)
+
+
+def test_pressure_floor_on_grid():
+    """The grid inversion applies the floor cell by cell and counts it: a
+    rough random state with a quarter of its cells at p = 1e-13 rho floors
+    exactly those cells."""
+    n = 8
+    prim, bf = _random_state(n, 77)
+    prim5 = prim[:5]
+    rng = np.random.default_rng(78)
+    cold = rng.random(prim5[0].shape) < 0.25
+    prim5[4] = np.where(cold, 1e-13 * prim5[0], prim5[4])
+    g = O.Grid(n, pfloor=1e-10)
+    cons, W = g.init(prim5, bf)
+    g.stats = O.Stats()
+    prim, it, nfail = g.c2p(cons, bf, W)
+    assert nfail == 0
+    assert g.stats.floors == int(cold.sum()) > 0
+    np.testing.assert_array_equal(prim[4][cold], 1e-10 * prim[0][cold])
+    np.testing.assert_allclose(prim[4][~cold], prim5[4][~cold], rtol=1e-9)
+
+
+# ---------------------------------------------------------------- MP5 (LC)
+def test_mp5_keeps_parabola_cell_averages():
+    """From cell averages of any parabola the curvature bounds of Suresh &
+    Huynh contain the exact face value, so MP5 returns it even where the
+    monotonicity test engages the limiter: the large-curvature value
+    v_i + (v_i - v_{i-1})/2 + (beta/3) d is the exact value plus
+    (beta - 1) d/3 (d the common second difference, beta = 4), and the
+    median value is the exact value minus d/3.  This bounds the LC constant
+    from below (beta >= 1); its value 4 is the published choice."""
+    h = 1.0
+    rng = np.random.default_rng(12)
+    engaged = 0
+    for _ in range(3000):
+        # a + c2 (x - x0)^2, vertex anywhere on or near the stencil
+        c2 = rng.choice([-1.0, 1.0]) * 10 ** rng.uniform(-1, 2)
+        x0 = rng.uniform(-3.0, 3.0)
+        a0 = rng.normal()
+        coef = [a0 + c2 * x0 * x0, -2 * c2 * x0, c2]
+        P = np.polynomial.polynomial.Polynomial(coef)
+        avg = [_cell_avg_poly(coef, (m - 0.5) * h, (m + 0.5) * h) for m in range(-2, 3)]
+        exact = P(0.5 * h)
+        s = np.array(avg)
+        vmp = s[2] + (lambda a, b: (min(a, b) if a > 0 and b > 0 else
+                                    (max(a, b) if a < 0 and b < 0 else 0.0)))(
+            s[3] - s[2], 4 * (s[2] - s[1]))
+        vor = (2 * s[0] - 13 * s[1] + 47 * s[2] + 27 * s[3] - 3 * s[4]) / 60
+        engaged += (vor - s[2]) * (vor - vmp) > 1e-10
+        assert O.mp5(avg) == pytest.approx(exact, abs=1e-12 * max(1.0, abs(c2)))
+    assert engaged > 300
