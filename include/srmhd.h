@@ -19,7 +19,8 @@
  *     contiguous, x fastest: a[(k*ny + j)*nx + i].
  *   - bface[d] holds B_d on the +d face of each cell (x_{i+1/2} for d = 0).
  *   - The caller owns every buffer; the library allocates no device memory.
- *     Scratch comes from srmhd_buffers.work (size from srmhd_work_bytes).
+ *     Scratch comes from srmhd_buffers.work (size from srmhd_work_bytes), or
+ *     for srmhd_mlp_forward_noalloc from a fixed static device array.
  *   - All GPU work is enqueued on the stream given to srmhd_create, in order;
  *     only calls documented as "syncs" wait for the stream.
  *   - Return value: SRMHD_OK (0) or a negative SRMHD_E_* code.  Argument
@@ -275,6 +276,22 @@ int srmhd_mlp_quantize(const float *params, uint16_t *w_bf16, int n, void *strea
 int srmhd_mlp_forward(const float *params, const uint16_t *w_bf16, const float *x,
                       float *y, void *cache, int batch, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * forward pass of srmhd_mlp_forward (same kernels, the same y bit for bit)
+ * without the activation cache.  Its scratch is a static device array inside
+ * the library, 18 MiB per GPU, held until the process ends, so batch is
+ * limited to 1..65536 (SRMHD_E_INVAL beyond, before any launch, with the
+ * message in srmhd_last_error(NULL)).  params, w_bf16, x, y: device, as in
+ * srmhd_mlp_forward; stream: a hipStream_t of the current device.  No device
+ * memory is allocated or freed.  Every call on a GPU shares that GPU's
+ * scratch: calls that overlap on one GPU (different streams or host threads
+ * without ordering) race; calls in order on one stream do not.
+ * Asynchronous. */
+#define SRMHD_MLP_NOALLOC_MAX_BATCH 65536
+int srmhd_mlp_forward_noalloc(const float *params, const uint16_t *w_bf16,
+                              const float *x, float *y, int batch, void *stream);
+
 /* Mean squared error over the 2*batch outputs into *loss (device) and its
  * gradient with respect to y into cache.  Asynchronous. */
 int srmhd_mlp_loss_grad(const float *y, const float *t, void *cache, float *loss,
@@ -296,7 +313,8 @@ int srmhd_mlp_adam(float *params, uint16_t *w_bf16, float *m, float *v,
  * it with the sources beside it to refuse a stale build. */
 const char *srmhd_build_id(void);
 
-/* Message of the last failure on ctx (NULL ctx: last creation failure). */
+/* Message of the last failure on ctx (NULL ctx: the last failure of
+ * srmhd_create or of a call without a context). */
 const char *srmhd_last_error(const srmhd_ctx *ctx);
 const char *srmhd_strerror(int code);
 

@@ -119,6 +119,7 @@ def lib():
         L.srmhd_mlp_cache_bytes.restype = C.c_size_t
         L.srmhd_mlp_quantize.argtypes = [_VP, _VP, C.c_int, _VP]
         L.srmhd_mlp_forward.argtypes = [_VP, _VP, _VP, _VP, _VP, C.c_int, _VP]
+        L.srmhd_mlp_forward_noalloc.argtypes = [_VP, _VP, _VP, _VP, C.c_int, _VP]
         L.srmhd_mlp_loss_grad.argtypes = [_VP, _VP, _VP, _VP, C.c_int, _VP]
         L.srmhd_mlp_backward.argtypes = [_VP, _VP, _VP, C.c_int, _VP]
         L.srmhd_mlp_adam.argtypes = [_VP, _VP, _VP, _VP, _VP, C.c_int, C.c_float, C.c_float,
@@ -278,6 +279,14 @@ def srmhd_mlp_quantize(params, w_bf16, n, stream=0):
 def srmhd_mlp_forward(params, w_bf16, x, y, cache, batch, stream=0):
     _check(lib().srmhd_mlp_forward(_vp(params), _vp(w_bf16), _vp(x), _vp(y), _vp(cache),
                                    int(batch), _vp(stream)))
+
+
+MLP_NOALLOC_MAX_BATCH = 65536
+
+
+def srmhd_mlp_forward_noalloc(params, w_bf16, x, y, batch, stream=0):
+    _check(lib().srmhd_mlp_forward_noalloc(_vp(params), _vp(w_bf16), _vp(x), _vp(y),
+                                           int(batch), _vp(stream)))
 
 
 def srmhd_mlp_loss_grad(y, t, cache, loss, batch, stream=0):

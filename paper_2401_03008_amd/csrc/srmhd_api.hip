@@ -49,6 +49,11 @@ struct srmhd_ctx {
 
 static std::string g_create_error;
 
+namespace srmhd {
+// Failure message of a call without a context (srmhd_last_error(NULL)).
+void set_call_error(const char* msg) { g_create_error = msg; }
+}  // namespace srmhd
+
 #ifndef SRMHD_BUILD_ID
 #define SRMHD_BUILD_ID "unknown"
 #endif

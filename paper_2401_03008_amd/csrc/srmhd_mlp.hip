@@ -10,8 +10,22 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 
 namespace srmhd {
+
+// Message for srmhd_last_error(NULL) (srmhd_api.hip).
+void set_call_error(const char* msg);
+
+// Scratch of srmhd_mlp_forward_noalloc: the BF16 activations of one batch
+// (input tile X, hidden H1, H2; feature-major, batch padded to 16), for
+// batches of up to kNoAllocMaxBatch samples.  Each GPU the library runs on
+// holds its own copy until the process ends; host code reaches it only
+// through the address hipGetSymbolAddress returns on that device.
+constexpr int kNoAllocMaxBatch = 65536;
+constexpr size_t kNoAllocBytes = (size_t)(2 * 16 + 2 * 64 + 2 * 64) * kNoAllocMaxBatch;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
 namespace {
 
 struct GemmArgs {
@@ -203,6 +217,47 @@ int check() { return hipGetLastError() == hipSuccess ? SRMHD_OK : SRMHD_E_HIP; }
 
 bool batch_ok(int batch) { return batch > 0 && batch <= kLossParts * 256 / kMlpOut; }
 
+// Device address of `scratch` on each device, looked up once per device
+// (with that device current) at the first no-alloc call there.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_of_current_device(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return SRMHD_E_HIP;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return SRMHD_E_HIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return SRMHD_OK;
+}
+
+// The three network layers of one forward pass: x (batch x 5) -> X -> H1 ->
+// H2 -> y (batch x 2).  Z1, Z2 (the FP32 pre-activations, kept for the
+// backward pass) are written when non-null.
+void forward_layers(const float* params, const uint16_t* w_bf16, const float* x, float* y,
+                    uint16_t* X, float* Z1, uint16_t* H1, float* Z2, uint16_t* H2, int batch,
+                    hipStream_t s) {
+  const long long bp = (batch + 15) / 16 * 16;
+  hipLaunchKernelGGL(k_pack_x, dim3((batch * kMlpIn + 255) / 256), dim3(256), 0, s, x, batch,
+                     (int)bp, X);
+  GemmArgs g = gemm_args(kMlpH, batch, kMlpIn, w_bf16 + kOffW1, kMlpIn, 1, X, bp, 1);
+  g.mode = 1; g.Cf = Z1; g.scm = bp; g.scn = 1; g.Cb = H1; g.sbm = bp; g.sbn2 = 1;
+  g.bias = params + kOffB1;
+  gemm(g, s);
+  g = gemm_args(kMlpH, batch, kMlpH, w_bf16 + kOffW2, kMlpH, 1, H1, bp, 1);
+  g.mode = 1; g.Cf = Z2; g.scm = bp; g.scn = 1; g.Cb = H2; g.sbm = bp; g.sbn2 = 1;
+  g.bias = params + kOffB2;
+  gemm(g, s);
+  g = gemm_args(kMlpOut, batch, kMlpH, w_bf16 + kOffW3, kMlpH, 1, H2, bp, 1);
+  g.mode = 2; g.Cf = y; g.scm = 1; g.scn = kMlpOut; g.bias = params + kOffB3;
+  gemm(g, s);
+}
+
 }  // namespace
 }  // namespace srmhd
 
@@ -226,22 +281,33 @@ int srmhd_mlp_forward(const float* params, const uint16_t* w_bf16, const float* 
                       void* cache, int batch, void* stream) {
   if (!params || !w_bf16 || !x || !y || !cache || !batch_ok(batch)) return SRMHD_E_INVAL;
   if (((uintptr_t)cache) % 256) return SRMHD_E_INVAL;
-  hipStream_t s = (hipStream_t)stream;
   const Cache c = cache_of(cache, batch);
-  const long long bp = (batch + 15) / 16 * 16;
-  hipLaunchKernelGGL(k_pack_x, dim3((batch * kMlpIn + 255) / 256), dim3(256), 0, s, x, batch,
-                     (int)bp, c.X);
-  GemmArgs g = gemm_args(kMlpH, batch, kMlpIn, w_bf16 + kOffW1, kMlpIn, 1, c.X, bp, 1);
-  g.mode = 1; g.Cf = c.Z1; g.scm = bp; g.scn = 1; g.Cb = c.H1; g.sbm = bp; g.sbn2 = 1;
-  g.bias = params + kOffB1;
-  gemm(g, s);
-  g = gemm_args(kMlpH, batch, kMlpH, w_bf16 + kOffW2, kMlpH, 1, c.H1, bp, 1);
-  g.mode = 1; g.Cf = c.Z2; g.scm = bp; g.scn = 1; g.Cb = c.H2; g.sbm = bp; g.sbn2 = 1;
-  g.bias = params + kOffB2;
-  gemm(g, s);
-  g = gemm_args(kMlpOut, batch, kMlpH, w_bf16 + kOffW3, kMlpH, 1, c.H2, bp, 1);
-  g.mode = 2; g.Cf = y; g.scm = 1; g.scn = kMlpOut; g.bias = params + kOffB3;
-  gemm(g, s);
+  forward_layers(params, w_bf16, x, y, c.X, c.Z1, c.H1, c.Z2, c.H2, batch, (hipStream_t)stream);
+  return check();
+}
+
+int srmhd_mlp_forward_noalloc(const float* params, const uint16_t* w_bf16, const float* x,
+                              float* y, int batch, void* stream) {
+  if (!params || !w_bf16 || !x || !y) {
+    set_call_error("mlp_forward_noalloc: a pointer is NULL");
+    return SRMHD_E_INVAL;
+  }
+  if (batch < 1 || batch > kNoAllocMaxBatch) {
+    set_call_error("mlp_forward_noalloc: batch must be in 1..65536 (the size of the "
+                         "library's static scratch)");
+    return SRMHD_E_INVAL;
+  }
+  void* base = nullptr;
+  if (scratch_of_current_device(&base) != SRMHD_OK) {
+    set_call_error("mlp_forward_noalloc: hipGetSymbolAddress of the scratch failed");
+    return SRMHD_E_HIP;
+  }
+  // X | H1 | H2, each 256-byte aligned (bp * 2 bytes is a multiple of 32)
+  const size_t bp = (size_t)((batch + 15) / 16 * 16);
+  uint16_t* X = (uint16_t*)base;
+  uint16_t* H1 = X + al(2 * 16 * bp) / 2;
+  uint16_t* H2 = H1 + al(2 * kMlpH * bp) / 2;
+  forward_layers(params, w_bf16, x, y, X, nullptr, H1, nullptr, H2, batch, (hipStream_t)stream);
   return check();
 }
 
