@@ -15,8 +15,9 @@
  *
  * Conventions for every entry point
  *   - Device pointers are HIP device addresses on the context's device; host
- *     pointers are marked (host).  Every grid array is nx*ny*nz doubles,
- *     contiguous, x fastest: a[(k*ny + j)*nx + i].
+ *     pointers are marked (host).  Every grid array is nx*ny*nz doubles
+ *     (nx*ny*(nz + 2 ghost_z) for a slab context), contiguous, x fastest:
+ *     a[(k*ny + j)*nx + i].
  *   - bface[d] holds B_d on the +d face of each cell (x_{i+1/2} for d = 0).
  *   - The caller owns every buffer; the library allocates no device memory.
  *     Scratch comes from srmhd_buffers.work (size from srmhd_work_bytes), or
@@ -87,6 +88,20 @@ typedef struct {
                        interpolation (3, -20, 90, 60, -5)/128.  div B in the
                        diagnostics is then the same sixth-order difference
                        of the face B, which the HO curl keeps constant. */
+  int ghost_z;      /* 0: the box is periodic in z.  G > 0: the context holds
+                       one z-slab of a larger box periodic in z, split into
+                       slabs for domain decomposition (Sec. 3 decomposes over
+                       ranks; the enlarged halo of the closing section lets
+                       one exchange per Runge-Kutta stage suffice): nz and lz
+                       are the slab's interior planes and length, and every
+                       grid array holds nx*ny*(nz + 2G) values, the G planes
+                       below and above the interior being ghost copies of the
+                       neighbouring slabs' edge planes.  G >= 4 (>= 8 with
+                       high_order): one stage's update of a plane reads the
+                       state of the 4 planes below and 3 above it (8 and 7
+                       with HO).  nz >= G.  x and y stay periodic.  Such a
+                       context steps only through srmhd_stage_begin/_end,
+                       with srmhd_halo_pack/_unpack after every stage. */
 } srmhd_config;
 
 typedef struct {
@@ -199,6 +214,49 @@ int srmhd_get_state(srmhd_ctx *ctx, double *const cons[5], double *const bface[3
 int srmhd_set_state(srmhd_ctx *ctx, const double *const cons[5],
                     const double *const bface[3], const double *w, double t,
                     long step);
+
+/* ---------------------------------------------------------------------
+ * One Runge-Kutta stage in two halves, for a driver that splits a box into
+ * z-slabs (config.ghost_z) and exchanges ghost planes between them once per
+ * stage; on a periodic context (ghost_z = 0) the same sequence gives the
+ * srmhd_step result bit for bit.  A step is stages 1..3 (SSP-RK3) or 1..2
+ * (SSP-RK2), each stage_begin(s) followed by stage_end(s), in order;
+ * anything else returns SRMHD_E_STATE.  Between stages, and after the last
+ * one, the slabs exchange ghost planes (srmhd_halo_pack on each slab,
+ * srmhd_halo_unpack on its neighbours).  Other entry points that touch the
+ * state (step, rhs, get/set_state, get_primitives, init, harvest,
+ * mlp_guess) return SRMHD_E_STATE while a step is under way.
+ *
+ * srmhd_stage_begin: INT + inversion of every plane, REC + upwind fluxes
+ * and fast speeds (Sec. 3); in stage 1 also this slab's max over its
+ * interior cells of sum_d max(a+,a-)_d/dx_d.  Asynchronous.
+ *
+ * srmhd_local_amax (after stage_begin(1)): that maximum into amax_dev
+ * (device, one double), for a max-reduction over the slabs.  Asynchronous.
+ *
+ * srmhd_stage_end: in stage 1, dt = cfl / *amax_dev (device; the max over
+ * all slabs; NULL = this slab's own maximum), or dt_fixed; then UCT, DER and
+ * the stage's Runge-Kutta update.  amax_dev is ignored in later stages.
+ * Asynchronous. */
+int srmhd_stage_begin(srmhd_ctx *ctx, int stage);
+int srmhd_local_amax(srmhd_ctx *ctx, double *amax_dev);
+int srmhd_stage_end(srmhd_ctx *ctx, int stage, const double *amax_dev);
+
+/* Ghost planes of a slab context (ghost_z = G > 0): the exchanged values are
+ * the 9 state arrays D, Sx, Sy, Sz, U, face B_x, B_y, B_z and the Newton
+ * guess W (G planes of each) of the current stage's state.
+ * srmhd_halo_count: *n (host) = 9*G*nx*ny, the doubles of one side's buffer.
+ * srmhd_halo_pack: side 0 = the G lowest interior planes (for the slab
+ * below), side 1 = the G highest (for the slab above), into buf (device,
+ * array-major: array a's planes at buf[a*G*nx*ny]).
+ * srmhd_halo_unpack: buf into the ghost planes of side 0 (below the
+ * interior) or 1 (above), from the neighbour's pack of its facing side.
+ * SRMHD_E_STATE on a periodic context or between the halves of a stage.
+ * Asynchronous on the context's stream; a buffer from another context's
+ * stream needs the caller's ordering. */
+int srmhd_halo_count(const srmhd_ctx *ctx, size_t *n);
+int srmhd_halo_pack(srmhd_ctx *ctx, int side, double *buf);
+int srmhd_halo_unpack(srmhd_ctx *ctx, int side, const double *buf);
 
 /* Per-kernel timing with HIP events recorded on the context's stream around
  * every launch (adds a small host/queue overhead per launch; off by

@@ -42,7 +42,8 @@ class Config(C.Structure):
                 ("riemann", C.c_int), ("precision", C.c_int), ("guess", C.c_int),
                 ("newton_maxit", C.c_int), ("newton_tol", C.c_double),
                 ("pfloor", C.c_double), ("collect_stats", C.c_int),
-                ("recon", C.c_int), ("time_order", C.c_int), ("high_order", C.c_int)]
+                ("recon", C.c_int), ("time_order", C.c_int), ("high_order", C.c_int),
+                ("ghost_z", C.c_int)]
 
 
 class Buffers(C.Structure):
@@ -111,6 +112,12 @@ def lib():
         L.srmhd_set_state.argtypes = [_CTX, C.POINTER(_VP), C.POINTER(_VP), _VP, C.c_double,
                                       C.c_long]
         L.srmhd_mlp_guess.argtypes = [_CTX, _VP, _VP]
+        L.srmhd_stage_begin.argtypes = [_CTX, C.c_int]
+        L.srmhd_local_amax.argtypes = [_CTX, _VP]
+        L.srmhd_stage_end.argtypes = [_CTX, C.c_int, _VP]
+        L.srmhd_halo_count.argtypes = [_CTX, C.POINTER(C.c_size_t)]
+        L.srmhd_halo_pack.argtypes = [_CTX, C.c_int, _VP]
+        L.srmhd_halo_unpack.argtypes = [_CTX, C.c_int, _VP]
         L.srmhd_set_mlp.argtypes = [_CTX, _VP, _VP, C.POINTER(C.c_float)]
         L.srmhd_set_guess.argtypes = [_CTX, C.c_int]
         L.srmhd_harvest.argtypes = [_CTX, _VP, _VP, C.c_int, C.c_double, C.c_uint,
@@ -238,6 +245,33 @@ def srmhd_set_state(ctx, cons, bface, w, t, step):
 
 def srmhd_mlp_guess(ctx, out, w0=0):
     _check(lib().srmhd_mlp_guess(ctx, _VP(int(out)), _VP(int(w0 or 0) or None)), ctx)
+
+
+def srmhd_stage_begin(ctx, stage):
+    _check(lib().srmhd_stage_begin(ctx, int(stage)), ctx)
+
+
+def srmhd_local_amax(ctx, amax_dev):
+    _check(lib().srmhd_local_amax(ctx, _VP(int(amax_dev))), ctx)
+
+
+def srmhd_stage_end(ctx, stage, amax_dev=0):
+    """amax_dev: device pointer to the speed maximum over all slabs, or 0."""
+    _check(lib().srmhd_stage_end(ctx, int(stage), _VP(int(amax_dev or 0) or None)), ctx)
+
+
+def srmhd_halo_count(ctx):
+    n = C.c_size_t()
+    _check(lib().srmhd_halo_count(ctx, C.byref(n)), ctx)
+    return n.value
+
+
+def srmhd_halo_pack(ctx, side, buf):
+    _check(lib().srmhd_halo_pack(ctx, int(side), _VP(int(buf))), ctx)
+
+
+def srmhd_halo_unpack(ctx, side, buf):
+    _check(lib().srmhd_halo_unpack(ctx, int(side), _VP(int(buf))), ctx)
 
 
 def srmhd_build_id():

@@ -21,9 +21,15 @@ struct srmhd_ctx {
   hipStream_t stream;
   int device;
   GridDims g;
-  long long ncell;
+  long long ncell;  // cells of every grid array (ghost planes included)
   bool mixed;
   bool initialized;
+  // stage sequence of srmhd_stage_begin/_end: the next stage to begin
+  // (1-based), whether its first half ran, and whether the state the next
+  // stage reads is the work register (mid-step) or the caller's arrays
+  int next_stage;
+  bool half_done;
+  bool state_in_reg;
   DevScalars* sc;
   unsigned long long* counters;
   double* partial;
@@ -108,13 +114,24 @@ struct KTimer {
   }
 };
 
+// Planes of every grid array: the interior plus the ghost planes of a slab.
+int planes_of(const srmhd_config* c) { return c->nz + 2 * c->ghost_z; }
+
 std::string validate(const srmhd_config* c) {
   if (!c) return "config is NULL";
   if (c->nx < 1 || c->ny < 1 || c->nz < 1) return "nx, ny, nz must each be >= 1";
-  if ((long long)c->nx * c->ny * c->nz >= (1LL << 31)) return "nx*ny*nz must be < 2^31";
+  if (c->ghost_z < 0 || c->ghost_z > 64) return "ghost_z must be in 0..64";
+  if (c->ghost_z > 0) {
+    const int need = c->high_order ? 8 : 4;
+    if (c->ghost_z < need)
+      return c->high_order ? "ghost_z must be >= 8 with high_order" : "ghost_z must be >= 4";
+    if (c->nz < c->ghost_z) return "a slab needs nz >= ghost_z interior planes";
+  }
+  const long long nzp = planes_of(c);
+  if ((long long)c->nx * c->ny * nzp >= (1LL << 31)) return "nx*ny*nz must be < 2^31";
   // every launch is a 1D grid of tiles (at most 64 x 8 x 8 cells, tile rows
   // padded to groups of 8): its thread count must stay below 2^32
-  if ((double)(c->nx + 63) * (c->ny + 8) * (c->nz + 8) + 32768.0 * ((c->nx + 63) / 64) >=
+  if ((double)(c->nx + 63) * (c->ny + 8) * (nzp + 8) + 32768.0 * ((c->nx + 63) / 64) >=
       4294967295.0)
     return "box too large for one launch grid";
   if (!(c->lx > 0 && c->ly > 0 && c->lz > 0)) return "box lengths must be > 0";
@@ -148,7 +165,7 @@ struct Layout {
 
 Layout layout_of(const srmhd_config* c) {
   Layout L;
-  const size_t n = (size_t)c->nx * c->ny * c->nz;
+  const size_t n = (size_t)c->nx * c->ny * planes_of(c);
   L.off_sc = 0;
   L.off_cnt = align_up(sizeof(DevScalars));
   L.off_part = L.off_cnt + align_up(sizeof(unsigned long long) * kReplicas * CNT_N);
@@ -288,7 +305,9 @@ int guess_code(const srmhd_ctx* c) {
   return c->cfg.guess == SRMHD_GUESS_COLD ? 2 : (c->cfg.guess == SRMHD_GUESS_MLP ? 1 : 0);
 }
 
-void run_stage(srmhd_ctx* c, int stage, double* const* rhs_out) {
+// First half of a stage: INT + inversion, REC + face fluxes and speeds (and
+// the running CFL maximum in stage 1 and stage 0).
+void stage_first_half(srmhd_ctx* c, int stage) {
   const int guess = guess_code(c);
   const StageState st = stage_state(c, stage);
   if (c->mixed)
@@ -298,12 +317,35 @@ void run_stage(srmhd_ctx* c, int stage, double* const* rhs_out) {
   const bool cfl = stage <= 1;
   if (c->mixed) stage_flux<float>(c, st, cfl);
   else stage_flux<double>(c, st, cfl);
+}
+
+// Second half: dt in stage 1 (from amax_in, device, or the running maximum),
+// then UCT, DER and the update.
+void stage_second_half(srmhd_ctx* c, int stage, double* const* rhs_out, const double* amax_in) {
+  const StageState st = stage_state(c, stage);
   if (stage == 1) {
     KTimer kt(c, 8);
-    launch_dt(c->sc, c->cfg.cfl, c->cfg.dt_fixed, c->stream);
+    launch_dt(c->sc, c->cfg.cfl, c->cfg.dt_fixed, amax_in, c->stream);
   }
   if (c->mixed) stage_uct_update<float>(c, st, stage, rhs_out);
   else stage_uct_update<double>(c, st, stage, rhs_out);
+}
+
+void run_stage(srmhd_ctx* c, int stage, double* const* rhs_out) {
+  stage_first_half(c, stage);
+  stage_second_half(c, stage, rhs_out, nullptr);
+}
+
+// Internal code of stage s (1-based) of a step: SSP-RK3 1, 2, 3; SSP-RK2 1, 4.
+int stage_code(const srmhd_ctx* c, int s) { return (c->cfg.time_order == 2 && s == 2) ? 4 : s; }
+int stages_per_step(const srmhd_ctx* c) { return c->cfg.time_order == 2 ? 2 : 3; }
+
+// SRMHD_E_STATE while a step driven by srmhd_stage_begin/_end is under way.
+int check_between_steps(srmhd_ctx* c, const char* what) {
+  if (c->next_stage != 1 || c->half_done)
+    return fail(c, SRMHD_E_STATE,
+                std::string(what) + " while a step is under way (finish its stages first)");
+  return SRMHD_OK;
 }
 
 __global__ void k_take_amax(srmhd::DevScalars* sc, double* out) {
@@ -335,6 +377,7 @@ int srmhd_config_default(srmhd_config* cfg) {
   cfg->recon = SRMHD_REC_MP5;
   cfg->time_order = 3;
   cfg->high_order = 0;
+  cfg->ghost_z = 0;
   return SRMHD_OK;
 }
 
@@ -374,11 +417,21 @@ int srmhd_create(const srmhd_config* cfg, const srmhd_buffers* buf, void* stream
   }
   c->g.nx = cfg->nx;
   c->g.ny = cfg->ny;
-  c->g.nz = cfg->nz;
+  c->g.nz = planes_of(cfg);
   c->g.inv_dx[0] = cfg->nx / cfg->lx;
   c->g.inv_dx[1] = cfg->ny / cfg->ly;
   c->g.inv_dx[2] = cfg->nz / cfg->lz;
-  c->ncell = (long long)cfg->nx * cfg->ny * cfg->nz;
+  // interior planes, and the planes whose primitives the interior's fluxes
+  // read (3 beyond each edge; 5 with the HO differences)
+  const int G = cfg->ghost_z, reach = G > 0 ? (cfg->high_order ? 5 : 3) : 0;
+  c->g.zlo = G;
+  c->g.zhi = G + cfg->nz;
+  c->g.zplo = G - reach;
+  c->g.zphi = G + cfg->nz + reach;
+  c->ncell = (long long)cfg->nx * cfg->ny * c->g.nz;
+  c->next_stage = 1;
+  c->half_done = false;
+  c->state_in_reg = false;
   c->mixed = cfg->precision == SRMHD_MIXED;
   c->initialized = false;
   c->timing = false;
@@ -422,6 +475,7 @@ int srmhd_create(const srmhd_config* cfg, const srmhd_buffers* buf, void* stream
 
 int srmhd_init_from_prims(srmhd_ctx* c, const double* const prim5[5], const double* const bface[3]) {
   if (!c) return SRMHD_E_INVAL;
+  if (check_between_steps(c, "init_from_prims") != SRMHD_OK) return SRMHD_E_STATE;
   if (!prim5 || !bface) return fail(c, SRMHD_E_INVAL, "prim5/bface is NULL");
   for (int n = 0; n < 5; ++n)
     if (!prim5[n]) return fail(c, SRMHD_E_INVAL, "prim5 entry is NULL");
@@ -456,6 +510,11 @@ int srmhd_step(srmhd_ctx* c, int nsteps) {
   if (nsteps < 0) return fail(c, SRMHD_E_INVAL, "nsteps < 0");
   if (c->cfg.guess == SRMHD_GUESS_MLP && !c->mlp_set)
     return fail(c, SRMHD_E_STATE, "learned guess selected but no network set");
+  if (c->cfg.ghost_z > 0)
+    return fail(c, SRMHD_E_STATE,
+                "a slab context (ghost_z > 0) steps through srmhd_stage_begin/_end with a "
+                "ghost exchange after every stage");
+  if (check_between_steps(c, "step") != SRMHD_OK) return SRMHD_E_STATE;
   for (int s = 0; s < nsteps; ++s) {
     run_stage(c, 1, nullptr);
     if (c->cfg.time_order == 2) {
@@ -471,6 +530,7 @@ int srmhd_step(srmhd_ctx* c, int nsteps) {
 int srmhd_rhs(srmhd_ctx* c, double* const rhs[8], double* amax_dev) {
   if (!c) return SRMHD_E_INVAL;
   if (!c->initialized) return fail(c, SRMHD_E_STATE, "rhs before init_from_prims");
+  if (check_between_steps(c, "rhs") != SRMHD_OK) return SRMHD_E_STATE;
   if (!rhs || !amax_dev) return fail(c, SRMHD_E_INVAL, "rhs/amax is NULL");
   if (c->cfg.guess == SRMHD_GUESS_MLP && !c->mlp_set)
     return fail(c, SRMHD_E_STATE, "learned guess selected but no network set");
@@ -486,6 +546,7 @@ int srmhd_rhs(srmhd_ctx* c, double* const rhs[8], double* amax_dev) {
 int srmhd_get_primitives(srmhd_ctx* c, double* const prim[8]) {
   if (!c) return SRMHD_E_INVAL;
   if (!c->initialized) return fail(c, SRMHD_E_STATE, "get_primitives before init_from_prims");
+  if (check_between_steps(c, "get_primitives") != SRMHD_OK) return SRMHD_E_STATE;
   if (!prim) return fail(c, SRMHD_E_INVAL, "prim is NULL");
   for (int n = 0; n < 8; ++n)
     if (!prim[n]) return fail(c, SRMHD_E_INVAL, "prim entry is NULL");
@@ -499,6 +560,7 @@ int srmhd_get_state(srmhd_ctx* c, double* const cons[5], double* const bface[3],
                     double* t, long* step) {
   if (!c) return SRMHD_E_INVAL;
   if (!c->initialized) return fail(c, SRMHD_E_STATE, "get_state before the state is set");
+  if (check_between_steps(c, "get_state") != SRMHD_OK) return SRMHD_E_STATE;
   if (cons)
     for (int n = 0; n < 5; ++n)
       if (!cons[n]) return fail(c, SRMHD_E_INVAL, "cons entry is NULL");
@@ -524,6 +586,7 @@ int srmhd_get_state(srmhd_ctx* c, double* const cons[5], double* const bface[3],
 int srmhd_set_state(srmhd_ctx* c, const double* const cons[5], const double* const bface[3],
                     const double* w, double t, long step) {
   if (!c) return SRMHD_E_INVAL;
+  if (check_between_steps(c, "set_state") != SRMHD_OK) return SRMHD_E_STATE;
   if (!cons || !bface) return fail(c, SRMHD_E_INVAL, "cons/bface is NULL");
   for (int n = 0; n < 5; ++n)
     if (!cons[n]) return fail(c, SRMHD_E_INVAL, "cons entry is NULL");
@@ -557,6 +620,7 @@ int srmhd_set_state(srmhd_ctx* c, const double* const cons[5], const double* con
 int srmhd_mlp_guess(srmhd_ctx* c, float* out, double* w0) {
   if (!c) return SRMHD_E_INVAL;
   if (!c->initialized) return fail(c, SRMHD_E_STATE, "mlp_guess before the state is set");
+  if (check_between_steps(c, "mlp_guess") != SRMHD_OK) return SRMHD_E_STATE;
   if (!c->mlp_set) return fail(c, SRMHD_E_STATE, "mlp_guess needs srmhd_set_mlp first");
   if (!out) return fail(c, SRMHD_E_INVAL, "out is NULL");
   C2PArgs a;
@@ -579,6 +643,84 @@ int srmhd_mlp_guess(srmhd_ctx* c, float* out, double* w0) {
   a.mlp_w0 = w0;
   launch_c2p(a, false, c->stream);
   return check_launch(c, "mlp_guess");
+}
+
+int srmhd_stage_begin(srmhd_ctx* c, int stage) {
+  if (!c) return SRMHD_E_INVAL;
+  if (!c->initialized) return fail(c, SRMHD_E_STATE, "stage_begin before the state is set");
+  if (c->cfg.guess == SRMHD_GUESS_MLP && !c->mlp_set)
+    return fail(c, SRMHD_E_STATE, "learned guess selected but no network set");
+  if (stage < 1 || stage > stages_per_step(c))
+    return fail(c, SRMHD_E_INVAL, "stage must be 1..3 (SSP-RK3) or 1..2 (SSP-RK2)");
+  if (c->half_done || stage != c->next_stage)
+    return fail(c, SRMHD_E_STATE, "stage_begin out of order (expected stage " +
+                                      std::to_string(c->next_stage) +
+                                      (c->half_done ? "'s end" : "") + ")");
+  stage_first_half(c, stage_code(c, stage));
+  c->half_done = true;
+  return check_launch(c, "stage_begin");
+}
+
+int srmhd_local_amax(srmhd_ctx* c, double* amax_dev) {
+  if (!c) return SRMHD_E_INVAL;
+  if (!amax_dev) return fail(c, SRMHD_E_INVAL, "amax_dev is NULL");
+  if (!(c->half_done && c->next_stage == 1))
+    return fail(c, SRMHD_E_STATE, "local_amax needs stage_begin(1) first");
+  launch_local_amax(c->sc, amax_dev, c->stream);
+  return check_launch(c, "local_amax");
+}
+
+int srmhd_stage_end(srmhd_ctx* c, int stage, const double* amax_dev) {
+  if (!c) return SRMHD_E_INVAL;
+  if (!c->half_done || stage != c->next_stage)
+    return fail(c, SRMHD_E_STATE, "stage_end without the matching stage_begin");
+  const int code = stage_code(c, stage);
+  stage_second_half(c, code, nullptr, stage == 1 ? amax_dev : nullptr);
+  c->half_done = false;
+  const bool last = stage == stages_per_step(c);
+  c->next_stage = last ? 1 : stage + 1;
+  c->state_in_reg = !last;
+  return check_launch(c, "stage_end");
+}
+
+int srmhd_halo_count(const srmhd_ctx* c, size_t* n) {
+  if (!c || !n) return SRMHD_E_INVAL;
+  *n = (size_t)9 * c->cfg.ghost_z * c->cfg.nx * c->cfg.ny;
+  return SRMHD_OK;
+}
+
+namespace {
+int halo_copy(srmhd_ctx* c, int side, double* buf, bool pack) {
+  if (!c) return SRMHD_E_INVAL;
+  const char* what = pack ? "halo_pack" : "halo_unpack";
+  if (c->cfg.ghost_z == 0)
+    return fail(c, SRMHD_E_STATE, std::string(what) + " on a context without ghost planes");
+  if (!c->initialized) return fail(c, SRMHD_E_STATE, std::string(what) + " before the state is set");
+  if (c->half_done)
+    return fail(c, SRMHD_E_STATE, std::string(what) + " between the halves of a stage");
+  if (side != 0 && side != 1) return fail(c, SRMHD_E_INVAL, "side must be 0 (below) or 1 (above)");
+  if (!buf) return fail(c, SRMHD_E_INVAL, "buf is NULL");
+  const int G = c->cfg.ghost_z, nz = c->cfg.nz;
+  HaloArgs h;
+  // the state the next stage reads: the work register mid-step, else the
+  // caller's arrays; W always
+  for (int n = 0; n < 5; ++n) h.a[n] = c->state_in_reg ? c->ureg[n] : c->buf.cons[n];
+  for (int d = 0; d < 3; ++d) h.a[5 + d] = c->state_in_reg ? c->ureg[5 + d] : c->buf.bface[d];
+  h.a[8] = c->buf.guess_w;
+  h.buf = buf;
+  h.plane = (long long)c->cfg.nx * c->cfg.ny;
+  h.G = G;
+  // pack: the interior's edge planes; unpack: the ghost planes beyond them
+  h.z0 = pack ? (side == 0 ? G : nz) : (side == 0 ? 0 : G + nz);
+  launch_halo(h, pack, c->stream);
+  return check_launch(c, what);
+}
+}  // namespace
+
+int srmhd_halo_pack(srmhd_ctx* c, int side, double* buf) { return halo_copy(c, side, buf, true); }
+
+int srmhd_halo_unpack(srmhd_ctx* c, int side, const double* buf) {
+  return halo_copy(c, side, const_cast<double*>(buf), false);
 }
 
 const char* srmhd_build_id(void) { return SRMHD_BUILD_ID; }
@@ -706,6 +848,7 @@ int srmhd_harvest(srmhd_ctx* c, float* feats, float* targets, int cap, double fr
                   int* n_out) {
   if (!c) return SRMHD_E_INVAL;
   if (!c->initialized) return fail(c, SRMHD_E_STATE, "harvest before init_from_prims");
+  if (check_between_steps(c, "harvest") != SRMHD_OK) return SRMHD_E_STATE;
   if (!feats || !targets || !n_out || cap <= 0 || !(frac > 0.0 && frac <= 1.0))
     return fail(c, SRMHD_E_INVAL, "bad harvest arguments");
   HarvestArgs a;

@@ -443,18 +443,19 @@ __global__ __launch_bounds__(kThreads) void k_c2p(C2PArgs a) {
       for (int n = 0; n < 5; ++n) a.prim32[n][c.id] = (float)pr[n];
       for (int d = 0; d < 3; ++d) a.prim32[5 + d][c.id] = (float)b[d];
     }
-    if (rc != 0) {
+    if (rc != 0 && c.k >= a.g.zplo && c.k < a.g.zphi) {
       const unsigned bit = rc == 1 ? kErrC2P : (rc == 2 ? kErrNonfinite : kErrPressure);
       atomicOr(a.err, bit);
     }
   }
   if (STATS) {
-    bc.add_uniform(CNT_ITERS, c.valid ? (unsigned)iters : 0u);
-    bc.add_uniform(CNT_CALLS, c.valid ? 1u : 0u);
-    bc.add_uniform(CNT_FAIL, (c.valid && rc != 0) ? 1u : 0u);
-    bc.add_uniform(CNT_FLOOR, (c.valid && floored) ? 1u : 0u);
-    if (MLP) bc.add_uniform(CNT_MLPFB, (c.valid && mlpfb) ? 1u : 0u);
-    bc.add_hist(CNT_HIST0, c.valid, iters < 31 ? iters : 31);
+    const bool in = c.valid && interior_plane(a.g, c.k);
+    bc.add_uniform(CNT_ITERS, in ? (unsigned)iters : 0u);
+    bc.add_uniform(CNT_CALLS, in ? 1u : 0u);
+    bc.add_uniform(CNT_FAIL, (in && rc != 0) ? 1u : 0u);
+    bc.add_uniform(CNT_FLOOR, (in && floored) ? 1u : 0u);
+    if (MLP) bc.add_uniform(CNT_MLPFB, (in && mlpfb) ? 1u : 0u);
+    bc.add_hist(CNT_HIST0, in, iters < 31 ? iters : 31);
     bc.flush(a.counters);
   }
 }
@@ -492,7 +493,7 @@ __device__ __forceinline__ unsigned hash_u32(unsigned x, unsigned seed) {
 
 __global__ __launch_bounds__(kThreads) void k_harvest(HarvestArgs a) {
   const Cell c = cell_of(a.g);
-  if (!c.valid) return;
+  if (!c.valid || !interior_plane(a.g, c.k)) return;
   const double r = hash_u32((unsigned)c.id, a.seed) * (1.0 / 4294967296.0);
   if (!(r < a.frac)) return;
   double u[5], b[3], pr[5];
@@ -614,6 +615,7 @@ __global__ __launch_bounds__((FluxTile<DIR, TS, STAGED>::kThreads)) void k_flux(
   }
   int nfb = 0;
   double cfl_sum = 0.0;
+  const bool inner = c.valid && interior_plane(a.g, c.k);
   if (c.valid) {
     // stencil point m (offset m - 2) of primitive n
     int idx[6];
@@ -684,7 +686,7 @@ __global__ __launch_bounds__((FluxTile<DIR, TS, STAGED>::kThreads)) void k_flux(
     a.fv[1][c.id] = L.vt1;
     a.fv[2][c.id] = R.vn;
     a.fv[3][c.id] = R.vt1;
-    if (CFL) {
+    if (CFL && inner) {
       // sum over d = 0, 1, 2 in that order; the other directions' speeds are
       // apm_other = {a+_T1, a-_T1, a+_T2, a-_T2}
       double m[3];
@@ -706,7 +708,7 @@ __global__ __launch_bounds__((FluxTile<DIR, TS, STAGED>::kThreads)) void k_flux(
     }
   }
   if (STATS) {
-    bc.add_uniform(CNT_FALLBACK, (unsigned)nfb);
+    bc.add_uniform(CNT_FALLBACK, inner ? (unsigned)nfb : 0u);
     bc.flush(a.counters);
   }
 }
@@ -1087,9 +1089,9 @@ template void launch_update<float>(int, const UpdArgs<float>&, bool, hipStream_t
 // ------------------------------------------------------------ timestep
 // dt = cfl / amax (or dt_fixed) once per step, from the first stage's speeds;
 // advances t and the step count and clears the running maximum.
-__global__ void k_dt(DevScalars* sc, double cfl, double dt_fixed) {
+__global__ void k_dt(DevScalars* sc, double cfl, double dt_fixed, const double* amax_in) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  const double amax = __longlong_as_double((long long)sc->amax_bits);
+  const double amax = amax_in ? *amax_in : __longlong_as_double((long long)sc->amax_bits);
   const double dt = dt_fixed > 0.0 ? dt_fixed : cfl / amax;
   if (!(dt > 0.0) || !isfinite(dt)) atomicOr(&sc->err, kErrDt);
   sc->dt = dt;
@@ -1099,8 +1101,40 @@ __global__ void k_dt(DevScalars* sc, double cfl, double dt_fixed) {
   sc->amax_bits = 0ull;
 }
 
-void launch_dt(DevScalars* sc, double cfl, double dt_fixed, hipStream_t s) {
-  hipLaunchKernelGGL(k_dt, dim3(1), dim3(64), 0, s, sc, cfl, dt_fixed);
+void launch_dt(DevScalars* sc, double cfl, double dt_fixed, const double* amax_in,
+               hipStream_t s) {
+  hipLaunchKernelGGL(k_dt, dim3(1), dim3(64), 0, s, sc, cfl, dt_fixed, amax_in);
+}
+
+__global__ void k_local_amax(const DevScalars* sc, double* out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0)
+    *out = __longlong_as_double((long long)sc->amax_bits);
+}
+
+void launch_local_amax(const DevScalars* sc, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_local_amax, dim3(1), dim3(64), 0, s, sc, out);
+}
+
+// Ghost planes: G contiguous planes of each of the 9 arrays (z is the
+// slowest index), one workgroup row per array.
+template <bool PACK>
+__global__ __launch_bounds__(256) void k_halo(HaloArgs h) {
+  const long long n = (long long)h.G * h.plane;
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const int a = blockIdx.y;
+  double* grid = h.a[a] + (long long)h.z0 * h.plane;
+  double* buf = h.buf + (long long)a * n;
+  if (PACK) buf[i] = grid[i];
+  else grid[i] = buf[i];
+}
+
+void launch_halo(const HaloArgs& h, bool pack, hipStream_t s) {
+  const long long n = (long long)h.G * h.plane;
+  if (n == 0) return;
+  const dim3 grid((unsigned)((n + 255) / 256), 9);
+  if (pack) hipLaunchKernelGGL(k_halo<true>, grid, dim3(256), 0, s, h);
+  else hipLaunchKernelGGL(k_halo<false>, grid, dim3(256), 0, s, h);
 }
 
 __global__ void k_zero_u64(unsigned long long* p, size_t n) {
@@ -1153,8 +1187,9 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce_partial(ReduceArgs a)
   const int nxy = a.g.nx * a.g.ny;
   for (long long q = beg + threadIdx.x; q < end; q += kReduceThreads) {
     const int id = (int)q;
-    for (int n = 0; n < 8; ++n) acc[n] += a.a[n][id];
     const int i = id % a.g.nx, j = (id / a.g.nx) % a.g.ny, k = id / nxy;
+    if (!interior_plane(a.g, k)) continue;
+    for (int n = 0; n < 8; ++n) acc[n] += a.a[n][id];
     double dv = 0.0;
     if (a.ho) {
       Cell c{};

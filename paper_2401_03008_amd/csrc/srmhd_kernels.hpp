@@ -44,10 +44,22 @@ struct DevScalars {
   unsigned long long harvest;  // slot counter of the training-pair harvest
 };
 
+// nz counts every plane of the arrays.  A z-slab context (ghost planes
+// below and above its interior) computes on all planes as if they were a
+// periodic box and keeps only the interior: the CFL maximum, the counters,
+// the diagnostics and the harvest take planes [zlo, zhi), and inversion
+// errors count on [zplo, zphi), the planes whose primitives the interior's
+// fluxes read (the outermost ghost planes hold wrapped, meaningless data).
+// A periodic box has zlo = zplo = 0, zhi = zphi = nz.
 struct GridDims {
   int nx, ny, nz;
   double inv_dx[3];
+  int zlo, zhi, zplo, zphi;
 };
+
+__host__ __device__ inline bool interior_plane(const GridDims& g, int k) {
+  return k >= g.zlo && k < g.zhi;
+}
 
 struct C2PArgs {
   GridDims g;
@@ -163,7 +175,19 @@ template <typename TS>
 void launch_uct(const Uct3Args<TS>& a, int k, int rec, hipStream_t s);  // orientation E_k
 template <typename TS>
 void launch_update(int stage, const UpdArgs<TS>& a, bool ho, hipStream_t s);
-void launch_dt(DevScalars* sc, double cfl, double dt_fixed, hipStream_t s);
+// amax_in (device, or null: the running maximum) is the speed maximum dt
+// takes.
+void launch_dt(DevScalars* sc, double cfl, double dt_fixed, const double* amax_in, hipStream_t s);
+void launch_local_amax(const DevScalars* sc, double* out, hipStream_t s);
+// Ghost-plane exchange of a z-slab: 9 arrays, planes [z0, z0 + G) each, to
+// (pack) or from (unpack) buf[a * G * plane + ...].
+struct HaloArgs {
+  double* a[9];
+  double* buf;
+  long long plane;  // nx * ny
+  int z0, G;
+};
+void launch_halo(const HaloArgs& h, bool pack, hipStream_t s);
 void launch_zero_u64(unsigned long long* p, size_t n, hipStream_t s);
 void launch_fill_f64(double* p, size_t n, double v, hipStream_t s);
 void launch_set_time(DevScalars* sc, double t, long long step, hipStream_t s);

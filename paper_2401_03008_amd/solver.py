@@ -5,6 +5,12 @@ in libsrmhd's HIP kernels.  State tensors (float64, shape (n, nz, ny, nx)):
 ``cons`` = D, Sx, Sy, Sz, U; ``bface`` = face B_x, B_y, B_z; ``W`` = Newton
 guess: the caller-owned buffers of the C ABI.  ``checkpoint``/``restore`` go
 through srmhd_get_state / srmhd_set_state.
+
+With ``ghost_z = G > 0`` the solver is one z-slab of a larger periodic box
+(nz interior planes of length L[2], plus G ghost planes below and above: the
+tensors have nz + 2G planes); it advances with ``stage_begin`` /
+``stage_end`` and a ghost exchange (``halo_pack`` / ``halo_unpack``) after
+every stage.
 """
 from __future__ import annotations
 
@@ -22,7 +28,8 @@ class Solver:
     def __init__(self, nx, ny=None, nz=None, L=(1.0, 1.0, 1.0), gamma_ad=4.0 / 3.0, cfl=0.5,
                  dt_fixed=0.0, riemann="hll", precision="fp64", guess="prev",
                  newton_maxit=50, newton_tol=1e-14, pfloor=0.0, collect_stats=True,
-                 recon="mp5", time_order=3, high_order=False, device="cuda:0", stream=None):
+                 recon="mp5", time_order=3, high_order=False, ghost_z=0, device="cuda:0",
+                 stream=None):
         if not torch.cuda.is_available():
             raise RuntimeError("Solver needs a HIP device (torch.cuda.is_available() is False)")
         ny = nx if ny is None else ny
@@ -40,8 +47,10 @@ class Solver:
         cfg.recon = _REC[recon]
         cfg.time_order = int(time_order)
         cfg.high_order = 1 if high_order else 0
+        cfg.ghost_z = int(ghost_z)
         self.cfg = cfg
-        self.shape = (nz, ny, nx)
+        self.ghost_z = int(ghost_z)
+        self.shape = (nz + 2 * self.ghost_z, ny, nx)
         wb = B.srmhd_work_bytes(cfg)
         f64 = dict(dtype=torch.float64, device=self.device)
         with torch.cuda.device(self.device):
@@ -163,3 +172,29 @@ class Solver:
         w0 = torch.empty(self.shape, dtype=torch.float64, device=self.device)
         B.srmhd_mlp_guess(self.ctx, out.data_ptr(), w0.data_ptr())
         return out, w0
+
+    # ------------------------------------------------- stages and ghost planes
+    def stage_begin(self, stage):
+        B.srmhd_stage_begin(self.ctx, stage)
+
+    def local_amax(self):
+        """This slab's speed maximum (a 1-element device tensor) after
+        stage_begin(1)."""
+        out = torch.empty(1, dtype=torch.float64, device=self.device)
+        B.srmhd_local_amax(self.ctx, out.data_ptr())
+        return out
+
+    def stage_end(self, stage, amax=None):
+        """amax: 1-element device tensor with the maximum over all slabs
+        (stage 1), or None for this slab's own."""
+        B.srmhd_stage_end(self.ctx, stage, amax.data_ptr() if amax is not None else 0)
+
+    def halo_pack(self, side):
+        """New device tensor with the G edge planes of side 0 (bottom) or 1
+        (top) of the 9 exchanged arrays."""
+        buf = torch.empty(B.srmhd_halo_count(self.ctx), dtype=torch.float64, device=self.device)
+        B.srmhd_halo_pack(self.ctx, side, buf.data_ptr())
+        return buf
+
+    def halo_unpack(self, side, buf):
+        B.srmhd_halo_unpack(self.ctx, side, buf.data_ptr())

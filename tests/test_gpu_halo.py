@@ -1,0 +1,200 @@
+"""z-slab contexts on one GPU: the periodic box split into slabs with ghost
+planes (config ghost_z), advanced by srmhd_stage_begin / srmhd_stage_end with
+one halo exchange (srmhd_halo_pack / _unpack, device buffers) after every
+stage and the timestep from the maximum over the slabs.  This is the one-GPU
+part of the domain decomposition the paper runs over ranks (Sec. 3), with the
+enlarged halo of its closing section: the split run must equal the undivided
+periodic run bit for bit (state, W, t), and its counters must add up to the
+undivided run's."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle as O  # noqa: E402
+from paper_2401_03008_amd import binding as B  # noqa: E402
+from paper_2401_03008_amd import inputs as I  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    O.build(force=False)
+
+
+def _solver(*a, **k):
+    from paper_2401_03008_amd.solver import Solver
+    return Solver(*a, **k)
+
+
+def _data(kind, n):
+    if kind == "cpa":
+        prim5, bf, _ = I.cpa(n, diagonal=True, device="cuda")
+    else:
+        prim5, bf = I.turbulence(n, sigma0=10.0, gamma_max=3.0, device="cuda")
+    return prim5, bf
+
+
+def _exchange(slabs):
+    bufs = [(S.halo_pack(0), S.halo_pack(1)) for S in slabs]
+    ns = len(slabs)
+    for s, S in enumerate(slabs):
+        S.halo_unpack(0, bufs[(s - 1) % ns][1])   # from the slab below: its top planes
+        S.halo_unpack(1, bufs[(s + 1) % ns][0])   # from the slab above: its bottom planes
+
+
+def _split_run(n, bounds, G, steps, kind, **kw):
+    prim5, bf = _data(kind, n)
+    slabs, z0 = [], 0
+    for h in bounds:
+        S = _solver(n, n, h, L=(1.0, 1.0, h / n), ghost_z=G, **kw)
+        idx = (torch.arange(h + 2 * G, device="cuda") + z0 - G) % n
+        S.init([a[idx] for a in prim5], [b[idx] for b in bf])
+        slabs.append(S)
+        z0 += h
+    _exchange(slabs)  # the lowest ghost planes' INT wrapped inside the slab
+    nst = 2 if kw.get("time_order", 3) == 2 else 3
+    for _ in range(steps):
+        for st in range(1, nst + 1):
+            for S in slabs:
+                S.stage_begin(st)
+            amax = None
+            if st == 1:
+                amax = torch.cat([S.local_amax() for S in slabs]).max().reshape(1)
+            for S in slabs:
+                S.stage_end(st, amax)
+            _exchange(slabs)
+    torch.cuda.synchronize()
+    return slabs
+
+
+def _interior(slabs, G):
+    cons = torch.cat([S.cons[:, G:S.shape[0] - G] for S in slabs], dim=1)
+    bface = torch.cat([S.bface[:, G:S.shape[0] - G] for S in slabs], dim=1)
+    W = torch.cat([S.W[G:S.shape[0] - G] for S in slabs], dim=0)
+    return cons, bface, W
+
+
+def _undivided(n, steps, kind, **kw):
+    prim5, bf = _data(kind, n)
+    S = _solver(n, **kw)
+    S.init(prim5, bf)
+    S.step(steps)
+    torch.cuda.synchronize()
+    return S
+
+
+CASES = [
+    ("cpa-2slabs", "cpa", [32, 32], 4, {}),
+    ("turb-3slabs-llf", "turb", [24, 20, 20], 4, {"riemann": "llf", "pfloor": 1e-10}),
+    ("cpa-ho", "cpa", [32, 32], 8, {"high_order": True}),
+    ("cpa-mixed", "cpa", [32, 32], 4, {"precision": "mixed"}),
+    ("turb-mc-rk2", "turb", [16, 48], 4, {"recon": "mc", "time_order": 2, "pfloor": 1e-10}),
+    ("turb-deeper-ghosts", "turb", [32, 32], 6, {"pfloor": 1e-10}),
+]
+
+
+@pytest.mark.parametrize("label,kind,bounds,G,kw", CASES, ids=[c[0] for c in CASES])
+def test_slabs_equal_undivided_bitwise(label, kind, bounds, G, kw):
+    n, steps = 64, 2
+    print(f"slabs {label}: n={n} bounds={bounds} G={G} {kw}", flush=True)
+    ref = _undivided(n, steps, kind, **kw)
+    slabs = _split_run(n, bounds, G, steps, kind, **kw)
+    cons, bface, W = _interior(slabs, G)
+    assert torch.equal(cons, ref.cons), "conserved variables differ"
+    assert torch.equal(bface, ref.bface), "face B differs"
+    assert torch.equal(W, ref.W), "Newton guess W differs"
+    t_ref, step_ref, dt_ref = ref.time()
+    for S in slabs:
+        t, st, dt = S.time()
+        assert (t, st, dt) == (t_ref, step_ref, dt_ref)
+    # counters and diagnostics count interior planes only: they add up
+    d_ref = ref.diagnostics()
+    ds = [S.diagnostics() for S in slabs]
+    for key in ("newton_iters", "newton_calls", "recon_fallbacks", "c2p_failures", "floors"):
+        assert sum(d[key] for d in ds) == d_ref[key], key
+    assert list(np.sum([d["newton_hist"] for d in ds], axis=0)) == d_ref["newton_hist"]
+    assert max(d["divb_max"] for d in ds) == d_ref["divb_max"]
+    for q in range(8):
+        tot = sum(d["sums"][q] for d in ds)
+        assert tot == pytest.approx(d_ref["sums"][q], rel=1e-12, abs=1e-9)
+    for S in slabs + [ref]:
+        S.close()
+
+
+def test_slabs_match_the_oracle():
+    """The split GPU run against the undivided CPU oracle (per-variable L1
+    relative error, parity tolerance 1e-12) on the rough turbulence box."""
+    n, steps, G = 32, 2, 4
+    slabs = _split_run(n, [16, 16], G, steps, "turb", riemann="llf", pfloor=1e-10)
+    cons, bface, _ = _interior(slabs, G)
+    prim5, bf = I.turbulence(n, sigma0=10.0, gamma_max=3.0)
+    g = O.Grid(n, riemann=1, pfloor=1e-10)
+    c_ref, W = g.init(prim5, bf)
+    b_ref = [b.copy() for b in bf]
+    g.step(c_ref, b_ref, W, steps)
+    got = [a.cpu().numpy() for a in cons] + [b.cpu().numpy() for b in bface]
+    for q, (a, r) in enumerate(zip(got, list(c_ref) + b_ref)):
+        err = np.abs(a - r).sum() / max(np.abs(r).sum(), r.size)
+        assert err <= 1e-12, (q, err)
+    for S in slabs:
+        S.close()
+
+
+def test_stage_calls_equal_step_on_a_periodic_box():
+    n = 32
+    prim5, bf, _ = I.cpa(n, diagonal=True, device="cuda")
+    A, Bs = _solver(n), _solver(n)
+    A.init(prim5, bf)
+    Bs.init(prim5, bf)
+    A.step(2)
+    for _ in range(2):
+        for st in (1, 2, 3):
+            Bs.stage_begin(st)
+            Bs.stage_end(st)
+    torch.cuda.synchronize()
+    assert torch.equal(A.cons, Bs.cons) and torch.equal(A.bface, Bs.bface)
+    assert torch.equal(A.W, Bs.W) and A.time() == Bs.time()
+    A.close()
+    Bs.close()
+
+
+def test_stage_sequence_and_slab_errors():
+    n, G = 32, 4
+    prim5, bf, _ = I.cpa(n, diagonal=True, device="cuda")
+    S = _solver(n, n, 16, L=(1.0, 1.0, 0.5), ghost_z=G)
+    idx = (torch.arange(16 + 2 * G, device="cuda") - G) % n
+    S.init([a[idx] for a in prim5], [b[idx] for b in bf])
+    with pytest.raises(B.SrmhdError) as e:
+        S.step(1)                          # a slab steps by stages only
+    assert e.value.code == B.SRMHD_E_STATE
+    with pytest.raises(B.SrmhdError) as e:
+        S.stage_end(1)                     # end before begin
+    assert e.value.code == B.SRMHD_E_STATE
+    with pytest.raises(B.SrmhdError) as e:
+        S.stage_begin(2)                   # stages in order
+    assert e.value.code == B.SRMHD_E_STATE
+    S.stage_begin(1)
+    for bad in (lambda: S.halo_pack(0), lambda: S.primitives(), lambda: S.get_state(),
+                lambda: S.stage_begin(1)):
+        with pytest.raises(B.SrmhdError) as e:
+            bad()                          # not between the halves of a stage
+        assert e.value.code == B.SRMHD_E_STATE
+    S.stage_end(1, S.local_amax())
+    with pytest.raises(B.SrmhdError) as e:
+        S.get_state()                      # not in the middle of a step
+    assert e.value.code == B.SRMHD_E_STATE
+    S.close()
+    P = _solver(n)
+    P.init(prim5, bf)
+    with pytest.raises(B.SrmhdError) as e:
+        P.halo_pack(0)                     # no ghost planes
+    assert e.value.code == B.SRMHD_E_STATE
+    P.close()
+    for kw in ({"ghost_z": 3}, {"ghost_z": 6, "high_order": True}, {"ghost_z": 20}):
+        with pytest.raises(B.SrmhdError) as e:
+            _solver(n, n, 16, L=(1.0, 1.0, 0.5), **kw)
+        assert e.value.code == B.SRMHD_E_INVAL
