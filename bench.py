@@ -42,10 +42,27 @@ FP32_PEAK_TFLOPS = 157.3    # MI355X FP32 vector (packed)
 STEP_BYTES = 560.0
 STEP_BYTES_RK2 = 352.0
 
-# Algorithmic HBM bytes and FP64/FP32 arithmetic operations per unit (cell,
-# face or edge) of each kernel class, for the plain FP64 form and the mixed
-# form, averaged over the class's launches in one step.  Bytes: every array
-# element the kernel must read or write, once.  flux: 7 primitives + normal B
+# State bytes per cell of each kernel class: the evolved arrays (the 8 state
+# arrays and W, FP64 in every form) it must read or write, once, averaged over
+# the class's launches in a step -- the per-cell-step traffic of the state,
+# 560 B over a step, apportioned to the kernels that touch it.  update: reads
+# the stage's input state (64 B) and, in stages 2 and 3, U^n (64 B), writes
+# the stage's output (64 B): (128 + 192 + 192)/3.  c2p: reads the state and W,
+# writes W.  The flux and UCT passes touch no state array beyond the normal
+# face B (their operands are intermediates).  The roofline's achieved
+# bandwidth and fraction use these bytes.
+STATE_BYTES = {"c2p": 80.0, "flux_x": 8.0, "flux_y": 8.0, "flux_z": 8.0,
+               "uct_x": 16.0, "uct_y": 16.0, "uct_z": 16.0, "update": 512.0 / 3,
+               "update_c2p": 176.0}
+# With the fused update + inversion (stages 1 and 2: 128 + 16 and 192 + 16 B,
+# W included), the plain update runs in stage 3 only.
+STATE_BYTES_FUSED_UPDATE = 192.0
+
+# Bytes and FP64/FP32 arithmetic operations per unit (cell, face or edge) of
+# each kernel class with its intermediates, for the plain FP64 form and the
+# mixed form, averaged over the class's launches in one step (reported beside
+# the state-byte roofline).  Bytes: every array element the kernel must read
+# or write, once.  flux: 7 primitives + normal B
 # in, 5 fluxes + a+- + 4 face velocities out (the z pass of stage 1 also reads
 # the x and y speeds for the CFL sum: (184 + 152 + 152)/3).  uct_k (one edge
 # orientation): the 4 velocities of the P faces, B_P and B_Q, and a+- of the
@@ -64,7 +81,13 @@ KERNEL_UNITS = {
     "uct_y": (88.0, 56.0, 640.0),
     "uct_z": (88.0, 56.0, 640.0),
     "update": (944.0 / 3, 764.0 / 3, 80.0),
+    # the update fused with the next stage's inversion (stages 1 and 2): also
+    # writes the primitives (FP64, or FP32 in the mixed form) and reads and
+    # writes W
+    "update_c2p": ((272.0 + 336.0) / 2 + 80.0, (212.0 + 276.0) / 2 + 48.0, 280.0),
 }
+# the plain update in stage 3 only (when stages 1 and 2 run fused)
+KERNEL_UNITS_FUSED_UPDATE = (336.0, 276.0, 80.0)
 # rocprofv3 kernel names of each class's FP64 launches in one step (name,
 # launches per step), for the HBM traffic read from the profiles
 PROFILED_KERNEL = {
@@ -78,6 +101,8 @@ PROFILED_KERNEL = {
     "uct_z": [("k_uct<2, double, 0, true>", 3)],
     "update": [("k_update<1, double>", 1), ("k_update<2, double>", 1),
                ("k_update<3, double>", 1)],
+    "update_c2p": [("k_update_c2p<1, double, false>", 1), ("k_update_c2p<2, double, false>", 1),
+                   ("k_update_c2p<3, double, false>", 1)],
 }
 
 
@@ -138,10 +163,10 @@ def stream_copy_gbs(gib=2, reps=5):
     return 2.0 * nb / (ms / 1e3) / 1e9
 
 
-def run_form(n, precision, steps, warmup, mlp=None, **scheme):
+def run_form(n, precision, steps, warmup, mlp=None, guess="mlp", **scheme):
     """Mcell-updates/s of one form on the diagonal CPA at n^3 (mlp: the
-    learned Newton guess; scheme: recon / time_order / high_order), then
-    Newton statistics over 2 more steps."""
+    learned Newton guess, in mode `guess`; scheme: recon / time_order /
+    high_order), then Newton statistics over 2 more steps."""
     import torch
     from paper_2401_03008_amd import inputs
     from paper_2401_03008_amd.solver import Solver
@@ -151,7 +176,7 @@ def run_form(n, precision, steps, warmup, mlp=None, **scheme):
     del prim5, bf
     if mlp is not None:
         S.set_mlp(mlp)
-        S.set_guess("mlp")
+        S.set_guess(guess)
     S.step(warmup)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -172,7 +197,7 @@ def run_form(n, precision, steps, warmup, mlp=None, **scheme):
     del prim5, bf
     if mlp is not None:
         S2.set_mlp(mlp)
-        S2.set_guess("mlp")
+        S2.set_guess(guess)
     S2.step(2)
     d = S2.diagnostics()
     S2.close()
@@ -194,7 +219,8 @@ def workload_label(n, precision="fp64", high_order=False, recon="mp5", time_orde
     scheme = ("point-value MP5, sixth-order INT/DER (HO)" if high_order else
               ("MP5" if recon == "mp5" else "linear MC"))
     prec = "FP64" if precision == "fp64" else "FP64 state, FP32 REC and face fluxes"
-    g = {"prev": "previous-W", "mlp": "learned", "cold": "cold"}[guess]
+    g = {"prev": "previous-W", "mlp": "learned (where no usable previous W)",
+         "mlp_all": "learned (every cell)", "cold": "cold"}[guess]
     return (f"CPA Alfven wave on the box diagonal, {n}^3, {prec}, {scheme} + HLL + UCT + "
             f"SSP-RK{time_order}, CFL 0.5, {g} Newton guess")
 
@@ -242,56 +268,78 @@ def cpu_baseline(seconds_target=15.0):
             "single_thread_sample": f"same wave, {nsteps1} steps on 1 thread ({el1:.1f} s)"}
 
 
+def _newton_row(d):
+    h = d["newton_hist"]
+    tot = max(sum(h), 1)
+    cdf, acc = [], 0
+    for c in h:
+        acc += c
+        cdf.append(acc / tot)
+    return {"mean_iters": round(d["newton_iters"] / max(d["newton_calls"], 1), 3),
+            "p50": next(i for i, c in enumerate(cdf) if c >= 0.5),
+            "p99": next(i for i, c in enumerate(cdf) if c >= 0.99),
+            "fallback_rate": round(d["mlp_fallbacks"] / max(d["newton_calls"], 1), 5),
+            "c2p_failures": d["c2p_failures"], "rc": d["rc"]}
+
+
 def newton_report_turbulence(n, mlp, steps=4):
     """Newton iterations per inversion on the turbulence set-up at n^3
-    (sigma0 = 10, Gamma up to 5) with the previous-step W, the learned guess
-    and a cold start (W0 = U): each from the same state (2 steps in), over
-    the same `steps` steps; mean/p50/p99 iterations, fallback rate, k_c2p ms,
-    and the learned run's L1 difference from the previous-W run."""
+    (sigma0 = 10, Gamma up to 5), all from the same state (2 steps in).
+    Warm, over `steps` steps: the previous-step W, the learned guess where no
+    usable previous W exists ("mlp": the previous W everywhere here), the
+    network first in every cell ("mlp_all"), and a cold start (W0 = U);
+    mean/p50/p99 iterations, fallback rate, k_c2p ms, and each run's L1
+    difference from the previous-W run.  Restart, the inversion of the
+    conserved state alone (no W): the method without the network (a start
+    from U) and the learned guess."""
     import torch
     from paper_2401_03008_amd import inputs
     from paper_2401_03008_amd.solver import Solver
     prim5, bf = inputs.turbulence(n, sigma0=10.0, gamma_max=5.0, device="cuda")
     rows, ref = {}, None
-    for guess in ("prev", "mlp", "cold"):
+    runs = [(g, False, steps) for g in ("prev", "mlp", "mlp_all", "cold")] + \
+        [(g, True, 0) for g in ("prev", "mlp")]
+    for guess, restart, nst in runs:
         S = Solver(n, pfloor=1e-10, collect_stats=True)
         S.init(prim5, bf)
         S.step(2)
-        if guess == "mlp":
-            S.set_mlp(mlp)
+        if restart:
+            st = S.get_state()
+            S.set_state(st["cons"], st["bface"], None, st["t"], st["step"])
+            del st
+        S.set_mlp(mlp)
         S.set_guess(guess)
         S.reset_counters()
         S.kernel_timing(True)
-        S.step(steps)
+        if restart:
+            S.primitives()  # one inversion of every cell
+        else:
+            S.step(nst)
         kt = S.kernel_times()
         S.kernel_timing(False)
         d = S.diagnostics(raise_on_error=False)
         S.set_guess("prev")
-        h = d["newton_hist"]
-        tot = max(sum(h), 1)
-        cdf, acc = [], 0
-        for c in h:
-            acc += c
-            cdf.append(acc / tot)
-        row = {"mean_iters": round(d["newton_iters"] / max(d["newton_calls"], 1), 3),
-               "p50": next(i for i, c in enumerate(cdf) if c >= 0.5),
-               "p99": next(i for i, c in enumerate(cdf) if c >= 0.99),
-               "fallback_rate": round(d["mlp_fallbacks"] / max(d["newton_calls"], 1), 5),
-               "c2p_ms": round(kt["c2p"][0] / max(kt["c2p"][1], 1), 4),
-               "c2p_failures": d["c2p_failures"], "rc": d["rc"]}
-        P = S.primitives()
-        if guess == "prev":
-            ref = P
-        else:
-            row["l1_rel_vs_prev"] = float((P - ref).abs().sum() / ref.abs().sum())
-            del P
-        rows[guess] = row
+        row = _newton_row(d)
+        row["c2p_ms"] = round(kt["c2p"][0] / max(kt["c2p"][1], 1), 4)
+        if not restart:  # all kernels, per step (the fused updates invert too)
+            row["step_ms"] = round(sum(v[0] for v in kt.values()) / nst, 3)
+        key = ("restart_" if restart else "") + guess
+        if not restart:
+            P = S.primitives()
+            if guess == "prev":
+                ref = P
+            else:
+                row["l1_rel_vs_prev"] = float((P - ref).abs().sum() / ref.abs().sum())
+                del P
+        rows[key] = row
         S.close()
         del S
         torch.cuda.empty_cache()
     del ref, prim5, bf
     torch.cuda.empty_cache()
-    rows["workload"] = f"turbulence {n}^3, sigma0 = 10, Gamma <= 5, {steps} steps after 2"
+    rows["workload"] = (f"turbulence {n}^3, sigma0 = 10, Gamma <= 5: {steps} steps after 2 "
+                        "(warm), or one inversion after 2 steps of the conserved state "
+                        "without W (restart_*)")
     return rows
 
 
@@ -309,9 +357,10 @@ def main():
                          "default scheme)")
     ap.add_argument("--recon", default="mp5", choices=["mp5", "mc"])
     ap.add_argument("--time-order", type=int, default=3, choices=[2, 3])
-    ap.add_argument("--guess", default="prev", choices=["prev", "mlp"],
+    ap.add_argument("--guess", default="prev", choices=["prev", "mlp", "mlp_all"],
                     help="Newton guess of the timed run: the previous W, or the learned "
-                         "network (trained first by the library's kernels)")
+                         "network (trained first by the library's kernels) where no usable "
+                         "previous W exists / first in every cell")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--no-forms", action="store_true",
@@ -356,7 +405,7 @@ def main():
         from paper_2401_03008_amd.learned import train_default
         net = train_default()[0]
         S.set_mlp(net)
-        S.set_guess("mlp")
+        S.set_guess(args.guess)
         print("[bench] learned guess trained and set", file=sys.stderr, flush=True)
     S.step(args.warmup)
     torch.cuda.synchronize()
@@ -394,16 +443,22 @@ def main():
             if cnt:
                 kernels[k] = {"avg_ms": kms / cnt, "launches": cnt, "share": kms / tot}
         dom = max((k for k in kernels if k in KERNEL_UNITS), key=lambda k: kt[k][0])
-        b64, bmx, fl = KERNEL_UNITS[dom]
+        fused = "update_c2p" in kernels
+        b64, bmx, fl = (KERNEL_UNITS_FUSED_UPDATE if (fused and dom == "update")
+                        else KERNEL_UNITS[dom])
         units = n ** 3
         avg_s = kernels[dom]["avg_ms"] / 1e3
-        bytes_per = (bmx if args.precision == "mixed" else b64) * units
+        bytes_with_inter = (bmx if args.precision == "mixed" else b64) * units
+        sb = STATE_BYTES_FUSED_UPDATE if (fused and dom == "update") else STATE_BYTES[dom]
+        bytes_per = sb * units
         flops_per = fl * units
         gbs = bytes_per / avg_s / 1e9
+        gbs_inter = bytes_with_inter / avg_s / 1e9
         tfl = flops_per / avg_s / 1e12
         fpeak = FP32_PEAK_TFLOPS if (args.precision == "mixed" and dom.startswith("flux")) else FP64_PEAK_TFLOPS
-        # the roof that binds is the one with the larger minimum time
-        if bytes_per / (HBM_PEAK_GBS * 1e9) >= flops_per / (fpeak * 1e12):
+        # the roof that binds is the one with the larger minimum time (the
+        # kernel's own traffic, intermediates included, decides it)
+        if bytes_with_inter / (HBM_PEAK_GBS * 1e9) >= flops_per / (fpeak * 1e12):
             roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None}
         else:
@@ -414,8 +469,12 @@ def main():
         if args.precision == "fp64" and n == 256 and default_scheme:
             roof["traffic"] = profiled_traffic(dom)
         roof.update({"kernel": dom, "avg_ms": round(kernels[dom]["avg_ms"], 4),
-                     "alg_bytes_per_launch": bytes_per, "alg_flops_per_launch": flops_per,
-                     "alu_tflops": round(tfl, 3), "hbm_gbs": round(gbs, 1)})
+                     "alg_bytes_per_launch": bytes_per, "state_bytes_per_cell": sb,
+                     "alg_flops_per_launch": flops_per,
+                     "alu_tflops": round(tfl, 3), "hbm_gbs": round(gbs, 1),
+                     "bytes_with_intermediates_per_launch": bytes_with_inter,
+                     "achieved_with_intermediates_gbs": round(gbs_inter, 1),
+                     "frac_with_intermediates": round(gbs_inter / HBM_PEAK_GBS, 4)})
         print(f"[bench] kernel timing: {json.dumps(kernels)}", file=sys.stderr, flush=True)
     S.close()
     copy_gbs = stream_copy_gbs()
@@ -442,9 +501,10 @@ def main():
         mlp, hist, npairs = train_default()
         train_s = time.perf_counter() - t0
         for prec in ("fp64", "mixed"):
-            key = f"{prec}+learned"
-            print(f"[bench] form {key} at {args.forms_n}^3", file=sys.stderr, flush=True)
-            forms[key] = run_form(args.forms_n, prec, max(5, args.steps // 2), 2, mlp=mlp)
+            for key, gmode in ((f"{prec}+learned", "mlp"), (f"{prec}+learned_all", "mlp_all")):
+                print(f"[bench] form {key} at {args.forms_n}^3", file=sys.stderr, flush=True)
+                forms[key] = run_form(args.forms_n, prec, max(5, args.steps // 2), 2, mlp=mlp,
+                                      guess=gmode)
         forms["learned_training"] = {"pairs": npairs, "adam_steps": 1500, "batch": 4096,
                                      "final_loss": hist[-1][1], "seconds": round(train_s, 2)}
         print(f"[bench] Newton report, turbulence {args.forms_n}^3", file=sys.stderr, flush=True)

@@ -49,7 +49,12 @@ extern "C" {
 
 enum { SRMHD_HLL = 0, SRMHD_LLF = 1 };
 enum { SRMHD_FP64 = 0, SRMHD_MIXED = 1 };
-enum { SRMHD_GUESS_PREV = 0, SRMHD_GUESS_MLP = 1, SRMHD_GUESS_COLD = 2 };
+/* Newton guess: the previous inversion's W; the learned guess where no usable
+ * previous W exists (W <= 0 or v^2(W) >= 1, e.g. after srmhd_set_state with
+ * no W), the previous W elsewhere; a cold start from W0 = U; or the learned
+ * guess first in every cell (the previous W where Newton from it fails). */
+enum { SRMHD_GUESS_PREV = 0, SRMHD_GUESS_MLP = 1, SRMHD_GUESS_COLD = 2,
+       SRMHD_GUESS_MLP_ALL = 3 };
 /* Reconstruction (REC, Sec. 3): MP5 (Suresh & Huynh 1997), or linear with the
  * monotonized-central limiter of van Leer (1977), the second-order option of
  * the benchmark section. */
@@ -70,8 +75,8 @@ typedef struct {
   double dt_fixed;  /* > 0: fixed dt instead of the CFL rule */
   int riemann;      /* SRMHD_HLL or SRMHD_LLF */
   int precision;    /* SRMHD_FP64, or SRMHD_MIXED: REC + face fluxes in FP32 */
-  int guess;        /* SRMHD_GUESS_PREV, _COLD, or _MLP (needs srmhd_set_mlp
-                       before the first step) */
+  int guess;        /* SRMHD_GUESS_PREV, _COLD, _MLP or _MLP_ALL (the last
+                       two need srmhd_set_mlp before the first step) */
   int newton_maxit; /* Newton iteration cap, 1..1000 (50) */
   double newton_tol;/* relative step tolerance on W (1e-14) */
   double pfloor;    /* pressure floor as a fraction of rho; 0 = none */
@@ -193,8 +198,9 @@ int srmhd_set_time(srmhd_ctx *ctx, double t, long step);
 
 /* The evolved state of the scheme (Sec. 3): the cell-centred conserved
  * variables D, S, U, the staggered face B, and the per-cell Newton guess W
- * (the previous inversion's converged W = rho h Gamma^2), with the simulated
- * time and step count.  Together they are a checkpoint: a context given them
+ * that the next inversion of this state starts from (the converged W =
+ * rho h Gamma^2 of the inversion before it), with the simulated time and
+ * step count.  Together they are a checkpoint: a context given them
  * by srmhd_set_state continues bit for bit as the one they came from.
  *
  * srmhd_get_state copies the state into caller device arrays (cons[5],
@@ -261,12 +267,14 @@ int srmhd_halo_unpack(srmhd_ctx *ctx, int side, const double *buf);
 /* Per-kernel timing with HIP events recorded on the context's stream around
  * every launch (adds a small host/queue overhead per launch; off by
  * default).  Classes, in order: 0 inversion, 1-3 face flux x/y/z, 4-6 UCT
- * edge fields E_x/E_y/E_z, 7 RK update, 8 timestep (the learned guess's
- * inference is part of class 0).
+ * edge fields E_x/E_y/E_z, 7 RK update, 8 timestep, 9 RK update fused with
+ * the inversion of its result for the next stage (periodic boxes without HO,
+ * previous-W or cold guess; class 0 then runs only where no stage before
+ * inverted the state) (the learned guess's inference is part of class 0).
  * srmhd_get_kernel_times syncs and
  * returns the accumulated milliseconds and launch counts since timing was
  * last enabled (ms, launches: host arrays of SRMHD_NKCLASS). */
-#define SRMHD_NKCLASS 9
+#define SRMHD_NKCLASS 10
 int srmhd_kernel_timing(srmhd_ctx *ctx, int enable);
 int srmhd_get_kernel_times(srmhd_ctx *ctx, double *ms, long *launches);
 
@@ -277,10 +285,16 @@ int srmhd_get_kernel_times(srmhd_ctx *ctx, double *ms, long *launches);
  * conserved state on which the inversion depends, log(U/D), |S|/U, B^2/U,
  * tau^2/(S^2 B^2 + 1e-300), log D (tau = S.B), standardised.  Outputs: the
  * standardised log(p/D) and log Gamma of the converged inversion, giving
- * W0 = D Gamma + g/(g-1) p Gamma^2.  Newton from the previous W stays the
- * fallback (when Newton from W0 does not converge or W0 is unusable) and the
- * convergence test is unchanged, so results agree with the plain form to the
- * Newton tolerance.
+ * W0 = D Gamma + g/(g-1) p Gamma^2.  With SRMHD_GUESS_MLP the network seeds
+ * Newton only in cells without a usable previous W (its guess is ~5e-3 from
+ * the root, the previous stage's W ~1e-4: measured, it costs iterations
+ * wherever a warm start exists), and a cold start from U is the fallback;
+ * once every cell holds a W from a completed inversion (after
+ * srmhd_init_from_prims, or after the first inversion that follows
+ * srmhd_set_state) the form runs the previous-W kernels.  With
+ * SRMHD_GUESS_MLP_ALL the network seeds every cell and the previous W is the
+ * fallback.  The convergence test is unchanged, so results agree with the
+ * plain form to the Newton tolerance.
  *
  * Parameter vector, FP32 master and BF16 copy in the same layout (rows are
  * output units): W1[64][5] | b1[64] | W2[64][64] | b2[64] | W3[2][64] | b3[2].

@@ -24,7 +24,7 @@ SRMHD_E_NONFINITE = -4
 SRMHD_E_STATE = -5
 SRMHD_HLL, SRMHD_LLF = 0, 1
 SRMHD_FP64, SRMHD_MIXED = 0, 1
-SRMHD_GUESS_PREV, SRMHD_GUESS_MLP, SRMHD_GUESS_COLD = 0, 1, 2
+SRMHD_GUESS_PREV, SRMHD_GUESS_MLP, SRMHD_GUESS_COLD, SRMHD_GUESS_MLP_ALL = 0, 1, 2, 3
 SRMHD_REC_MP5, SRMHD_REC_MC = 0, 1
 ERRBIT_C2P, ERRBIT_NONFINITE, ERRBIT_DT, ERRBIT_PRESSURE = 1, 2, 4, 8
 
@@ -338,9 +338,9 @@ def srmhd_mlp_adam(params, w_bf16, m, v, grad, n, lr, beta1, beta2, eps, t, stre
                                 _vp(stream)))
 
 
-NKCLASS = 9
+NKCLASS = 10
 KCLASS_NAMES = ["c2p", "flux_x", "flux_y", "flux_z", "uct_x", "uct_y", "uct_z",
-                "update", "dt"]
+                "update", "dt", "update_c2p"]
 
 
 def srmhd_kernel_timing(ctx, enable):

@@ -25,21 +25,27 @@ struct srmhd_ctx {
   bool mixed;
   bool initialized;
   // stage sequence of srmhd_stage_begin/_end: the next stage to begin
-  // (1-based), whether its first half ran, and whether the state the next
-  // stage reads is the work register (mid-step) or the caller's arrays
+  // (1-based) and whether its first half ran
   int next_stage;
   bool half_done;
-  bool state_in_reg;
+  // the primitives in the work buffer (and W) are the inversion of the
+  // current state, done by the last stage's fused update
+  bool prims_ready;
+  // every cell's W comes from a completed inversion (so it is usable: the
+  // learned guess of SRMHD_GUESS_MLP has nothing to seed)
+  bool w_complete;
   DevScalars* sc;
   unsigned long long* counters;
   double* partial;
-  double* ureg[8];  // RK stage register (U1, then U2)
+  double* ureg[8];  // RK stage register (U1, then U2; U2's face B in ureg2b)
+  double* ureg2b[3];  // face B of U2 (stage 2 must not overwrite U1's B in place)
   double* prim64[8];
   float* prim32[8];
   void* fhat[3][5];
   void* apm[3][2];
   void* fv[3][4];
   double* edge[3];
+
   std::string err;
   // per-kernel event timing
   bool timing;
@@ -141,7 +147,8 @@ std::string validate(const srmhd_config* c) {
   if (!(c->dt_fixed >= 0.0) || !std::isfinite(c->dt_fixed)) return "dt_fixed must be >= 0";
   if (c->riemann != SRMHD_HLL && c->riemann != SRMHD_LLF) return "riemann must be HLL or LLF";
   if (c->precision != SRMHD_FP64 && c->precision != SRMHD_MIXED) return "bad precision";
-  if (c->guess != SRMHD_GUESS_PREV && c->guess != SRMHD_GUESS_COLD && c->guess != SRMHD_GUESS_MLP)
+  if (c->guess != SRMHD_GUESS_PREV && c->guess != SRMHD_GUESS_COLD &&
+      c->guess != SRMHD_GUESS_MLP && c->guess != SRMHD_GUESS_MLP_ALL)
     return "bad guess mode";
   if (c->newton_maxit < 1 || c->newton_maxit > 1000) return "newton_maxit must be in 1..1000";
   if (!(c->newton_tol > 0.0 && c->newton_tol < 1e-3)) return "newton_tol must be in (0, 1e-3)";
@@ -173,9 +180,10 @@ Layout layout_of(const srmhd_config* c) {
   L.arr_bytes64 = align_up(n * sizeof(double));
   L.arr_bytes32 = align_up(n * sizeof(float));
   const bool mixed = c->precision == SRMHD_MIXED;
-  // RK register (8) + edge E (3) always FP64; prims FP64 (8) or FP32 (8); faces
+  // RK register (8 + 3 for U2's face B) + edge E (3) always FP64; prims FP64
+  // (8) or FP32 (8); faces
   // (15 fluxes + 6 speeds + 12 velocity states) in the flux precision.
-  L.n64 = 8 + 3 + (mixed ? 0 : 8 + 33);
+  L.n64 = 8 + 3 + 3 + (mixed ? 0 : 8 + 33);
   L.n32 = mixed ? 8 + 33 : 0;
   L.total = L.off_arr + L.n64 * L.arr_bytes64 + L.n32 * L.arr_bytes32;
   return L;
@@ -192,7 +200,8 @@ StageState stage_state(srmhd_ctx* c, int stage) {
   StageState s;
   const bool reg = stage >= 2;
   for (int n = 0; n < 5; ++n) s.cons[n] = reg ? c->ureg[n] : c->buf.cons[n];
-  for (int d = 0; d < 3; ++d) s.bf[d] = reg ? c->ureg[5 + d] : c->buf.bface[d];
+  for (int d = 0; d < 3; ++d)
+    s.bf[d] = stage == 3 ? c->ureg2b[d] : (reg ? c->ureg[5 + d] : c->buf.bface[d]);
   return s;
 }
 
@@ -229,8 +238,13 @@ void stage_flux(srmhd_ctx* c, const StageState& st, bool cfl) {
   }
 }
 
+C2PArgs c2p_args(srmhd_ctx* c, const StageState& st, double* const* prim64, float* const* prim32,
+                 int guess);
+int guess_code(const srmhd_ctx* c);
+
 template <typename TS>
-void stage_uct_update(srmhd_ctx* c, const StageState& st, int stage, double* const* rhs_out) {
+void stage_uct_update(srmhd_ctx* c, const StageState& st, int stage, double* const* rhs_out,
+                      bool fuse) {
   {
     Uct3Args<TS> a;
     a.g = c->g;
@@ -257,16 +271,25 @@ void stage_uct_update(srmhd_ctx* c, const StageState& st, int stage, double* con
   for (int n = 0; n < 8; ++n) {
     u.ucur[n] = n < 5 ? st.cons[n] : st.bf[n - 5];
     u.u0[n] = state[n];
-    u.uout[n] = stage >= 3 ? state[n] : c->ureg[n];  // the last stage writes U^{n+1}
+    // the last stage writes U^{n+1}; stage 2 keeps U1's face B intact
+    u.uout[n] = stage >= 3 ? state[n] : (stage == 2 && n >= 5 ? c->ureg2b[n - 5] : c->ureg[n]);
     u.rhs_out[n] = rhs_out ? rhs_out[n] : nullptr;
   }
   u.sc = c->sc;
-  KTimer kt(c, 7);
-  launch_update<TS>(stage, u, c->cfg.high_order != 0, c->stream);
+  if (fuse) {
+    // the next stage's inversion of this stage's output
+    const C2PArgs p = c2p_args(c, StageState{}, c->mixed ? nullptr : c->prim64,
+                               c->mixed ? c->prim32 : nullptr, guess_code(c));
+    KTimer kt(c, 9);
+    launch_update_c2p<TS>(stage, u, p, c->cfg.collect_stats != 0, c->stream);
+  } else {
+    KTimer kt(c, 7);
+    launch_update<TS>(stage, u, c->cfg.high_order != 0, c->stream);
+  }
 }
 
-void launch_c2p_into(srmhd_ctx* c, const StageState& st, double* const* prim64,
-                     float* const* prim32, int guess) {
+C2PArgs c2p_args(srmhd_ctx* c, const StageState& st, double* const* prim64, float* const* prim32,
+                 int guess) {
   C2PArgs a;
   a.g = c->g;
   for (int n = 0; n < 5; ++n) a.cons[n] = st.cons[n];
@@ -287,8 +310,15 @@ void launch_c2p_into(srmhd_ctx* c, const StageState& st, double* const* prim64,
   a.err = &c->sc->err;
   a.mlp_out = nullptr;
   a.mlp_w0 = nullptr;
+  return a;
+}
+
+void launch_c2p_into(srmhd_ctx* c, const StageState& st, double* const* prim64,
+                     float* const* prim32, int guess) {
+  const C2PArgs a = c2p_args(c, st, prim64, prim32, guess);
   KTimer kt(c, 0);
   launch_c2p(a, c->cfg.collect_stats != 0, c->stream);
+  c->w_complete = true;
 }
 
 // Device-to-device copy of one grid array on the context's stream (nothing
@@ -299,21 +329,43 @@ int copy_grid(srmhd_ctx* c, double* dst, const double* src, const char* what) {
                                      hipMemcpyDeviceToDevice, c->stream), what);
 }
 
-// One RK stage (1..3 of SSP-RK3; 1 and 4 of SSP-RK2), or stage 0 = L(U)
-// into rhs_out.
+// The kernels' guess code of the next inversion: the SRMHD_GUESS_* value
+// (see k_c2p), except that SRMHD_GUESS_MLP runs as the previous-W guess once
+// every cell has a W from a completed inversion (the network would seed no
+// cell).
 int guess_code(const srmhd_ctx* c) {
-  return c->cfg.guess == SRMHD_GUESS_COLD ? 2 : (c->cfg.guess == SRMHD_GUESS_MLP ? 1 : 0);
+  if (c->cfg.guess == SRMHD_GUESS_MLP && c->w_complete) return SRMHD_GUESS_PREV;
+  return c->cfg.guess;
 }
 
-// First half of a stage: INT + inversion, REC + face fluxes and speeds (and
-// the running CFL maximum in stage 1 and stage 0).
+bool learned_guess(const srmhd_ctx* c) {
+  return c->cfg.guess == SRMHD_GUESS_MLP || c->cfg.guess == SRMHD_GUESS_MLP_ALL;
+}
+
+// Whether a stage's update also inverts its output for the next stage
+// (k_update_c2p): periodic boxes, face-average INT, previous-W or cold
+// guess.  The sequence of inversions (inputs and W chain) is the same as
+// with a separate inversion at the start of each stage.
+bool fused_update(const srmhd_ctx* c) {
+  const int g = guess_code(c);
+  return c->cfg.ghost_z == 0 && !c->cfg.high_order &&
+         (g == SRMHD_GUESS_PREV || g == SRMHD_GUESS_COLD);
+}
+
+// First half of a stage (1..3 of SSP-RK3; 1 and 4 of SSP-RK2; 0 = L(U)):
+// INT + inversion (unless the previous stage's update already inverted this
+// state), REC + face fluxes and speeds (and the running CFL maximum in
+// stage 1 and stage 0).
 void stage_first_half(srmhd_ctx* c, int stage) {
   const int guess = guess_code(c);
   const StageState st = stage_state(c, stage);
-  if (c->mixed)
-    launch_c2p_into(c, st, nullptr, c->prim32, guess);
-  else
-    launch_c2p_into(c, st, c->prim64, nullptr, guess);
+  if (!(c->prims_ready && fused_update(c) && stage >= 1)) {
+    if (c->mixed)
+      launch_c2p_into(c, st, nullptr, c->prim32, guess);
+    else
+      launch_c2p_into(c, st, c->prim64, nullptr, guess);
+  }
+  c->prims_ready = false;
   const bool cfl = stage <= 1;
   if (c->mixed) stage_flux<float>(c, st, cfl);
   else stage_flux<double>(c, st, cfl);
@@ -327,8 +379,13 @@ void stage_second_half(srmhd_ctx* c, int stage, double* const* rhs_out, const do
     KTimer kt(c, 8);
     launch_dt(c->sc, c->cfg.cfl, c->cfg.dt_fixed, amax_in, c->stream);
   }
-  if (c->mixed) stage_uct_update<float>(c, st, stage, rhs_out);
-  else stage_uct_update<double>(c, st, stage, rhs_out);
+  // stages 1 and 2 (the last stage writes into U^n's arrays, which its
+  // neighbours' re-derived face B would still read)
+  const bool fuse = (stage == 1 || stage == 2) && !rhs_out && fused_update(c);
+  if (c->mixed) stage_uct_update<float>(c, st, stage, rhs_out, fuse);
+  else stage_uct_update<double>(c, st, stage, rhs_out, fuse);
+  c->prims_ready = fuse;
+  if (fuse) c->w_complete = true;
 }
 
 void run_stage(srmhd_ctx* c, int stage, double* const* rhs_out) {
@@ -431,7 +488,8 @@ int srmhd_create(const srmhd_config* cfg, const srmhd_buffers* buf, void* stream
   c->ncell = (long long)cfg->nx * cfg->ny * c->g.nz;
   c->next_stage = 1;
   c->half_done = false;
-  c->state_in_reg = false;
+  c->prims_ready = false;
+  c->w_complete = false;
   c->mixed = cfg->precision == SRMHD_MIXED;
   c->initialized = false;
   c->timing = false;
@@ -452,6 +510,7 @@ int srmhd_create(const srmhd_config* cfg, const srmhd_buffers* buf, void* stream
   auto takeT = [&]() -> void* { return c->mixed ? (void*)take32() : (void*)take64(); };
   for (int n = 0; n < 8; ++n) c->ureg[n] = take64();
   for (int k = 0; k < 3; ++k) c->edge[k] = take64();
+  for (int d = 0; d < 3; ++d) c->ureg2b[d] = take64();
   for (int n = 0; n < 8; ++n) {
     c->prim64[n] = c->mixed ? nullptr : take64();
     c->prim32[n] = c->mixed ? take32() : nullptr;
@@ -501,6 +560,8 @@ int srmhd_init_from_prims(srmhd_ctx* c, const double* const prim5[5], const doub
                   c->stream);
   const int rc = check_launch(c, "init_from_prims");
   if (rc == SRMHD_OK) c->initialized = true;
+  c->prims_ready = false;
+  c->w_complete = true;  // W = rho h Gamma^2 of the initial data
   return rc;
 }
 
@@ -508,7 +569,7 @@ int srmhd_step(srmhd_ctx* c, int nsteps) {
   if (!c) return SRMHD_E_INVAL;
   if (!c->initialized) return fail(c, SRMHD_E_STATE, "step before init_from_prims");
   if (nsteps < 0) return fail(c, SRMHD_E_INVAL, "nsteps < 0");
-  if (c->cfg.guess == SRMHD_GUESS_MLP && !c->mlp_set)
+  if (learned_guess(c) && !c->mlp_set)
     return fail(c, SRMHD_E_STATE, "learned guess selected but no network set");
   if (c->cfg.ghost_z > 0)
     return fail(c, SRMHD_E_STATE,
@@ -532,7 +593,7 @@ int srmhd_rhs(srmhd_ctx* c, double* const rhs[8], double* amax_dev) {
   if (!c->initialized) return fail(c, SRMHD_E_STATE, "rhs before init_from_prims");
   if (check_between_steps(c, "rhs") != SRMHD_OK) return SRMHD_E_STATE;
   if (!rhs || !amax_dev) return fail(c, SRMHD_E_INVAL, "rhs/amax is NULL");
-  if (c->cfg.guess == SRMHD_GUESS_MLP && !c->mlp_set)
+  if (learned_guess(c) && !c->mlp_set)
     return fail(c, SRMHD_E_STATE, "learned guess selected but no network set");
   for (int n = 0; n < 8; ++n)
     if (!rhs[n]) return fail(c, SRMHD_E_INVAL, "rhs entry is NULL");
@@ -550,9 +611,10 @@ int srmhd_get_primitives(srmhd_ctx* c, double* const prim[8]) {
   if (!prim) return fail(c, SRMHD_E_INVAL, "prim is NULL");
   for (int n = 0; n < 8; ++n)
     if (!prim[n]) return fail(c, SRMHD_E_INVAL, "prim entry is NULL");
-  if (c->cfg.guess == SRMHD_GUESS_MLP && !c->mlp_set)
+  if (learned_guess(c) && !c->mlp_set)
     return fail(c, SRMHD_E_STATE, "learned guess selected but no network set");
   launch_c2p_into(c, stage_state(c, 0), prim, nullptr, guess_code(c));
+  c->prims_ready = false;  // W moved: the next stage inverts afresh
   return check_launch(c, "get_primitives");
 }
 
@@ -572,7 +634,8 @@ int srmhd_get_state(srmhd_ctx* c, double* const cons[5], double* const bface[3],
     rc = copy_grid(c, cons[n], c->buf.cons[n], "get_state copy");
   for (int d = 0; bface && d < 3 && rc == SRMHD_OK; ++d)
     rc = copy_grid(c, bface[d], c->buf.bface[d], "get_state copy");
-  if (rc == SRMHD_OK && w) rc = copy_grid(c, w, c->buf.guess_w, "get_state copy");
+  if (rc == SRMHD_OK && w)
+    rc = copy_grid(c, w, c->buf.guess_w, "get_state copy");
   if (rc != SRMHD_OK) return rc;
   double tt = 0.0, dt = 0.0;
   long st = 0;
@@ -614,6 +677,8 @@ int srmhd_set_state(srmhd_ctx* c, const double* const cons[5], const double* con
   launch_set_time(c->sc, t, step, c->stream);
   rc = check_launch(c, "set_state");
   if (rc == SRMHD_OK) c->initialized = true;
+  c->prims_ready = false;
+  c->w_complete = false;  // a given W is checked cell by cell at the next inversion
   return rc;
 }
 
@@ -648,7 +713,7 @@ int srmhd_mlp_guess(srmhd_ctx* c, float* out, double* w0) {
 int srmhd_stage_begin(srmhd_ctx* c, int stage) {
   if (!c) return SRMHD_E_INVAL;
   if (!c->initialized) return fail(c, SRMHD_E_STATE, "stage_begin before the state is set");
-  if (c->cfg.guess == SRMHD_GUESS_MLP && !c->mlp_set)
+  if (learned_guess(c) && !c->mlp_set)
     return fail(c, SRMHD_E_STATE, "learned guess selected but no network set");
   if (stage < 1 || stage > stages_per_step(c))
     return fail(c, SRMHD_E_INVAL, "stage must be 1..3 (SSP-RK3) or 1..2 (SSP-RK2)");
@@ -679,7 +744,6 @@ int srmhd_stage_end(srmhd_ctx* c, int stage, const double* amax_dev) {
   c->half_done = false;
   const bool last = stage == stages_per_step(c);
   c->next_stage = last ? 1 : stage + 1;
-  c->state_in_reg = !last;
   return check_launch(c, "stage_end");
 }
 
@@ -702,10 +766,11 @@ int halo_copy(srmhd_ctx* c, int side, double* buf, bool pack) {
   if (!buf) return fail(c, SRMHD_E_INVAL, "buf is NULL");
   const int G = c->cfg.ghost_z, nz = c->cfg.nz;
   HaloArgs h;
-  // the state the next stage reads: the work register mid-step, else the
-  // caller's arrays; W always
-  for (int n = 0; n < 5; ++n) h.a[n] = c->state_in_reg ? c->ureg[n] : c->buf.cons[n];
-  for (int d = 0; d < 3; ++d) h.a[5 + d] = c->state_in_reg ? c->ureg[5 + d] : c->buf.bface[d];
+  // the state the next stage reads (the work registers mid-step, else the
+  // caller's arrays), and W
+  const StageState st = stage_state(c, stage_code(c, c->next_stage));
+  for (int n = 0; n < 5; ++n) h.a[n] = const_cast<double*>(st.cons[n]);
+  for (int d = 0; d < 3; ++d) h.a[5 + d] = st.bf[d];
   h.a[8] = c->buf.guess_w;
   h.buf = buf;
   h.plane = (long long)c->cfg.nx * c->cfg.ny;
@@ -811,6 +876,7 @@ int srmhd_set_time(srmhd_ctx* c, double t, long step) {
 
 int srmhd_set_mlp(srmhd_ctx* c, const float* params, const uint16_t* w_bf16, const float* norm) {
   if (!c) return SRMHD_E_INVAL;
+  c->prims_ready = false;
   if (!params || !w_bf16 || !norm) return fail(c, SRMHD_E_INVAL, "params/w_bf16/norm is NULL");
   if (reinterpret_cast<uintptr_t>(w_bf16) % 8 != 0)
     return fail(c, SRMHD_E_INVAL, "w_bf16 must be 8-byte aligned");
@@ -836,9 +902,11 @@ int srmhd_set_mlp(srmhd_ctx* c, const float* params, const uint16_t* w_bf16, con
 
 int srmhd_set_guess(srmhd_ctx* c, int guess) {
   if (!c) return SRMHD_E_INVAL;
-  if (guess != SRMHD_GUESS_PREV && guess != SRMHD_GUESS_COLD && guess != SRMHD_GUESS_MLP)
+  c->prims_ready = false;
+  if (guess != SRMHD_GUESS_PREV && guess != SRMHD_GUESS_COLD && guess != SRMHD_GUESS_MLP &&
+      guess != SRMHD_GUESS_MLP_ALL)
     return fail(c, SRMHD_E_INVAL, "bad guess mode");
-  if (guess == SRMHD_GUESS_MLP && !c->mlp_set)
+  if ((guess == SRMHD_GUESS_MLP || guess == SRMHD_GUESS_MLP_ALL) && !c->mlp_set)
     return fail(c, SRMHD_E_STATE, "learned guess needs srmhd_set_mlp first");
   c->cfg.guess = guess;
   return SRMHD_OK;

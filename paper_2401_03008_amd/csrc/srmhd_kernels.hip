@@ -369,9 +369,14 @@ __device__ int con2prim(const double* u, double bx, double by, double bz, double
 }
 
 // Guess: the previous W (mode 0), a cold start from U (mode 2), or the
-// learned guess (mode 1): the network's (log(p/D), log Gamma) gives
-// W0 = D Gamma + g/(g-1) p Gamma^2; if Newton from W0 does not converge, or W0
-// is unusable, the inversion is redone from the previous W and counted.
+// learned guess W0 = D Gamma + g/(g-1) p Gamma^2 from the network's
+// (log(p/D), log Gamma).  Mode 1: W0 seeds Newton only where the previous W
+// is unusable (W <= 0, not finite, or v^2(W) >= 1: after a restart from
+// conserved data alone); elsewhere Newton starts from the previous W as in
+// mode 0, and a workgroup evaluates the network only if one of its cells
+// needs it.  If Newton from W0 does not converge, or W0 is unusable, the
+// cell is redone from U (and counted).  Mode 3: W0 first in every cell,
+// redone from the previous W (and counted) where that fails.
 // PROBE (with MLP): write the network outputs and W0 of every cell and stop
 // before Newton (the same feature and inference code as the inversion).
 template <bool STATS, bool MLP, bool PROBE = false>
@@ -394,7 +399,21 @@ __global__ __launch_bounds__(kThreads) void k_c2p(C2PArgs a) {
   }
   double pr[5];
   double W = Wprev;
-  if (MLP) {
+  bool need = true;  // this lane seeds Newton with the network's guess
+  if (MLP && !PROBE && a.guess == 1) {
+    C2PIn q;
+    q.D = u[0];
+    q.U = u[4];
+    q.S2 = u[1] * u[1] + u[2] * u[2] + u[3] * u[3];
+    q.B2 = b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
+    const double tau = u[1] * b[0] + u[2] * b[1] + u[3] * b[2];
+    q.tau2 = tau * tau;
+    q.gf = (a.gam - 1.0) / a.gam;
+    double v2, iw, iwb;
+    need = c.valid && !c2p_usable(q, Wprev, v2, iw, iwb);
+  }
+  // the inference is workgroup-wide (its LDS hand-offs use barriers)
+  if (MLP && (PROBE || a.guess != 1 || __syncthreads_or(need ? 1 : 0))) {
     const double S2 = u[1] * u[1] + u[2] * u[2] + u[3] * u[3];
     const double B2 = b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
     const double tau = u[1] * b[0] + u[2] * b[1] + u[3] * b[2];
@@ -419,16 +438,20 @@ __global__ __launch_bounds__(kThreads) void k_c2p(C2PArgs a) {
       }
       return;
     }
-    if (c.valid) {
+    if (!need) W = Wprev;
+    if (c.valid && need) {
       rc = con2prim(u, b[0], b[1], b[2], a.gam, W, a.maxit, a.tol, a.pfloor, pr, iters, floored,
                     true);
       if (rc == 1 || rc == 4) {
         int it2 = 0;
-        W = Wprev;
+        // mode 3: the previous W; mode 1 (no usable previous W): from U
+        W = a.guess == 3 ? Wprev : -1.0;
         rc = con2prim(u, b[0], b[1], b[2], a.gam, W, a.maxit, a.tol, a.pfloor, pr, it2, floored);
         iters += it2;
         mlpfb = 1;
       }
+    } else if (c.valid) {
+      rc = con2prim(u, b[0], b[1], b[2], a.gam, W, a.maxit, a.tol, a.pfloor, pr, iters, floored);
     }
   } else if (c.valid) {
     rc = con2prim(u, b[0], b[1], b[2], a.gam, W, a.maxit, a.tol, a.pfloor, pr, iters, floored);
@@ -463,7 +486,7 @@ __global__ __launch_bounds__(kThreads) void k_c2p(C2PArgs a) {
 void launch_c2p(const C2PArgs& a, bool stats, hipStream_t s) {
   const dim3 grid = cell_grid(a.g);
   dim3 blk(kBlockX, kBlockY);
-  const bool mlp = a.guess == 1;
+  const bool mlp = a.guess == 1 || a.guess == 3;
   if (mlp && a.mlp_out) {
     hipLaunchKernelGGL((k_c2p<false, true, true>), grid, blk, 0, s, a);
     return;
@@ -878,6 +901,19 @@ template void launch_uct<float>(const Uct3Args<float>&, int, int, hipStream_t);
 // Stage 0 writes L only.  Stage 1 writes U1 to a work register, so U^n stays
 // in the caller's arrays and is read back by the later stages (no copy).
 
+// The stage's combination of U^n (u0), the stage input u and L(U) = r.  The
+// fused multiply-adds are written out, so every kernel that forms it (the
+// update, and the fused update re-deriving a neighbour's face B) rounds it
+// the same way.
+template <int STAGE>
+__device__ __forceinline__ double rk_combine(double u0, double u, double dt, double r) {
+  const double e = __builtin_fma(dt, r, u);  // u + dt r
+  if (STAGE == 1) return e;
+  if (STAGE == 2) return __builtin_fma(0.75, u0, 0.25 * e);
+  if (STAGE == 3) return __builtin_fma(1.0 / 3.0, u0, (2.0 / 3.0) * e);
+  return __builtin_fma(0.5, u0, 0.5 * e);
+}
+
 // The stage's combination of U with L(U) = r (stage 0: store r instead).
 template <int STAGE, typename TS>
 __device__ __forceinline__ void rk_apply(const UpdArgs<TS>& a, const Cell& c, const double* r) {
@@ -888,46 +924,149 @@ __device__ __forceinline__ void rk_apply(const UpdArgs<TS>& a, const Cell& c, co
   }
   const double dt = a.sc->dt;
 #pragma unroll
-  for (int n = 0; n < 8; ++n) {
-    const double u = a.ucur[n][c.id];
-    if (STAGE == 1) {
-      a.uout[n][c.id] = u + dt * r[n];
-    } else if (STAGE == 2) {
-      a.uout[n][c.id] = 0.75 * a.u0[n][c.id] + 0.25 * (u + dt * r[n]);
-    } else if (STAGE == 3) {
-      a.uout[n][c.id] = (1.0 / 3.0) * a.u0[n][c.id] + (2.0 / 3.0) * (u + dt * r[n]);
-    } else {
-      a.uout[n][c.id] = 0.5 * a.u0[n][c.id] + 0.5 * (u + dt * r[n]);
-    }
-  }
+  for (int n = 0; n < 8; ++n)
+    a.uout[n][c.id] =
+        rk_combine<STAGE>(STAGE == 1 ? 0.0 : a.u0[n][c.id], a.ucur[n][c.id], dt, r[n]);
 }
 
-// Second-order DER: one-sided differences of the +face fluxes and edges.
-template <int STAGE, typename TS>
-__global__ __launch_bounds__(kThreads) void k_update(UpdArgs<TS> a) {
-  const Cell c = cell_of_tile<kBlockY, 1>(a.g);
-  if (!c.valid) return;
+// -(curl E) on a face from the two edge-field differences across it:
+// -((a0 - a1) ia - (b0 - b1) ib), with its one fused multiply-add written out
+// (the same rounding wherever it is formed).
+__device__ __forceinline__ double curl_face(double a0, double a1, double ia, double b0, double b1,
+                                            double ib) {
+  return -__builtin_fma(a0 - a1, ia, -((b0 - b1) * ib));
+}
+
+// Second-order DER of cell c: one-sided differences of the +face fluxes and
+// the edge fields into r[8].
+template <typename TS>
+__device__ __forceinline__ void der2(const UpdArgs<TS>& a, const Cell& c, int im, int jm, int km,
+                                     double* r) {
   const double* ix = a.g.inv_dx;
   const double* Ex = a.e[0];
   const double* Ey = a.e[1];
   const double* Ez = a.e[2];
-  const int im = minus1(a.g, c, 0), jm = minus1(a.g, c, 1), km = minus1(a.g, c, 2);
   const int nb[3] = {im, jm, km};
-  double r[8];
 #pragma unroll
   for (int n = 0; n < 5; ++n) {
     double acc = 0.0;
 #pragma unroll
     for (int d = 0; d < 3; ++d)
-      acc += ((double)a.fhat[d][n][c.id] - (double)a.fhat[d][n][nb[d]]) * ix[d];
+      acc = __builtin_fma((double)a.fhat[d][n][c.id] - (double)a.fhat[d][n][nb[d]], ix[d], acc);
     r[n] = -acc;
   }
   const double ex0 = Ex[c.id], ey0 = Ey[c.id], ez0 = Ez[c.id];
-  r[5] = -((ez0 - Ez[jm]) * ix[1] - (ey0 - Ey[km]) * ix[2]);
-  r[6] = -((ex0 - Ex[km]) * ix[2] - (ez0 - Ez[im]) * ix[0]);
-  r[7] = -((ey0 - Ey[im]) * ix[0] - (ex0 - Ex[jm]) * ix[1]);
+  r[5] = curl_face(ez0, Ez[jm], ix[1], ey0, Ey[km], ix[2]);
+  r[6] = curl_face(ex0, Ex[km], ix[2], ez0, Ez[im], ix[0]);
+  r[7] = curl_face(ey0, Ey[im], ix[0], ex0, Ex[jm], ix[1]);
+}
+
+template <int STAGE, typename TS>
+__global__ __launch_bounds__(kThreads) void k_update(UpdArgs<TS> a) {
+  const Cell c = cell_of_tile<kBlockY, 1>(a.g);
+  if (!c.valid) return;
+  double r[8];
+  der2(a, c, minus1(a.g, c, 0), minus1(a.g, c, 1), minus1(a.g, c, 2), r);
   rk_apply<STAGE>(a, c, r);
 }
+
+// The update of stage STAGE (1 or 2: not the step's last) fused with the
+// inversion of its result (the next stage's INT + Newton, as k_c2p with guess
+// 0 or 2), for periodic boxes with the face-average INT: the updated state
+// never leaves the registers before the inversion reads it.  The face average
+// needs the updated B of the three minus faces; each cell re-derives them
+// with the same curl and the same combination as the neighbour that stores
+// them, so the centred B is the one k_c2p would read back.  That re-reads the
+// neighbours' input B, so the face-B output must not alias the stage's input
+// B (stage 2 writes it to its own register).  p carries the inversion's
+// outputs (primitives, W) and settings.
+template <int STAGE, typename TS, bool STATS>
+__global__ __launch_bounds__(kThreads) void k_update_c2p(UpdArgs<TS> a, C2PArgs p) {
+  __shared__ unsigned s_cnt[CNT_N];
+  BlockCounters bc;
+  if (STATS) bc.init(s_cnt);
+  const Cell c = cell_of_tile<kBlockY, 1>(a.g);
+  int iters = 0, rc = 0;
+  bool floored = false;
+  if (c.valid) {
+    const GridDims& g = a.g;
+    const int i1 = c.i == 0 ? g.nx - 1 : c.i - 1;
+    const int j1 = c.j == 0 ? g.ny - 1 : c.j - 1;
+    const int k1 = c.k == 0 ? g.nz - 1 : c.k - 1;
+    auto at = [&](int i, int j, int k) { return (k * g.ny + j) * g.nx + i; };
+    const int im = at(i1, c.j, c.k), jm = at(c.i, j1, c.k), km = at(c.i, c.j, k1);
+    double r[8];
+    der2(a, c, im, jm, km, r);
+    const double dt = a.sc->dt;
+    double un[8];
+#pragma unroll
+    for (int n = 0; n < 8; ++n) {
+      un[n] = rk_combine<STAGE>(STAGE == 1 ? 0.0 : a.u0[n][c.id], a.ucur[n][c.id], dt, r[n]);
+      a.uout[n][c.id] = un[n];
+    }
+    // the updated minus-face B: B_x at i-1, B_y at j-1, B_z at k-1
+    const int imjm = at(i1, j1, c.k), imkm = at(i1, c.j, k1), jmkm = at(c.i, j1, k1);
+    const double* ix = g.inv_dx;
+    const double* Ex = a.e[0];
+    const double* Ey = a.e[1];
+    const double* Ez = a.e[2];
+    const double rm[3] = {curl_face(Ez[im], Ez[imjm], ix[1], Ey[im], Ey[imkm], ix[2]),
+                          curl_face(Ex[jm], Ex[jmkm], ix[2], Ez[jm], Ez[imjm], ix[0]),
+                          curl_face(Ey[km], Ey[imkm], ix[0], Ex[km], Ex[jmkm], ix[1])};
+    const int nm[3] = {im, jm, km};
+    double b[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const double bm = rk_combine<STAGE>(STAGE == 1 ? 0.0 : a.u0[5 + d][nm[d]],
+                                          a.ucur[5 + d][nm[d]], dt, rm[d]);
+      b[d] = 0.5 * (bm + un[5 + d]);
+    }
+    double W = p.guess == 2 ? -1.0 : p.W[c.id];
+    double pr[5];
+    rc = con2prim(un, b[0], b[1], b[2], p.gam, W, p.maxit, p.tol, p.pfloor, pr, iters, floored);
+    p.W[c.id] = W;
+    if (p.prim64[0]) {
+      for (int n = 0; n < 5; ++n) p.prim64[n][c.id] = pr[n];
+      for (int d = 0; d < 3; ++d) p.prim64[5 + d][c.id] = b[d];
+    }
+    if (p.prim32[0]) {
+      for (int n = 0; n < 5; ++n) p.prim32[n][c.id] = (float)pr[n];
+      for (int d = 0; d < 3; ++d) p.prim32[5 + d][c.id] = (float)b[d];
+    }
+    if (rc != 0) {
+      const unsigned bit = rc == 1 ? kErrC2P : (rc == 2 ? kErrNonfinite : kErrPressure);
+      atomicOr(p.err, bit);
+    }
+  }
+  if (STATS) {
+    bc.add_uniform(CNT_ITERS, c.valid ? (unsigned)iters : 0u);
+    bc.add_uniform(CNT_CALLS, c.valid ? 1u : 0u);
+    bc.add_uniform(CNT_FAIL, (c.valid && rc != 0) ? 1u : 0u);
+    bc.add_uniform(CNT_FLOOR, (c.valid && floored) ? 1u : 0u);
+    bc.add_hist(CNT_HIST0, c.valid, iters < 31 ? iters : 31);
+    bc.flush(p.counters);
+  }
+}
+
+template <typename TS>
+void launch_update_c2p(int stage, const UpdArgs<TS>& a, const C2PArgs& p, bool stats,
+                       hipStream_t s) {
+  const dim3 grid = tile_grid<kBlockY, 1>(a.g);
+  const dim3 blk = tile_block<kBlockY, 1>();
+#define SRMHD_UC(ST)                                                                     \
+  if (stats) hipLaunchKernelGGL((k_update_c2p<ST, TS, true>), grid, blk, 0, s, a, p);    \
+  else hipLaunchKernelGGL((k_update_c2p<ST, TS, false>), grid, blk, 0, s, a, p);
+  if (stage == 1) {
+    SRMHD_UC(1)
+  } else {
+    SRMHD_UC(2)
+  }
+#undef SRMHD_UC
+}
+template void launch_update_c2p<double>(int, const UpdArgs<double>&, const C2PArgs&, bool,
+                                        hipStream_t);
+template void launch_update_c2p<float>(int, const UpdArgs<float>&, const C2PArgs&, bool,
+                                       hipStream_t);
 
 // HO DER: sixth-order differences (der6) of the face fluxes and edge fields.
 // Each direction differentiates seven arrays: its five face fluxes and the

@@ -177,6 +177,11 @@ template <typename TS>
 void launch_update(int stage, const UpdArgs<TS>& a, bool ho, hipStream_t s);
 // amax_in (device, or null: the running maximum) is the speed maximum dt
 // takes.
+// The update of stage 1 or 2 fused with the inversion of its output
+// (periodic box, face-average INT, guess 0 or 2); p.cons/p.bf are not read.
+template <typename TS>
+void launch_update_c2p(int stage, const UpdArgs<TS>& a, const C2PArgs& p, bool stats,
+                       hipStream_t s);
 void launch_dt(DevScalars* sc, double cfl, double dt_fixed, const double* amax_in, hipStream_t s);
 void launch_local_amax(const DevScalars* sc, double* out, hipStream_t s);
 // Ghost-plane exchange of a z-slab: 9 arrays, planes [z0, z0 + G) each, to

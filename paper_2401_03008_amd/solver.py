@@ -20,7 +20,8 @@ from . import binding as B
 
 _PREC = {"fp64": B.SRMHD_FP64, "mixed": B.SRMHD_MIXED}
 _RIEM = {"hll": B.SRMHD_HLL, "llf": B.SRMHD_LLF}
-_GUESS = {"prev": B.SRMHD_GUESS_PREV, "mlp": B.SRMHD_GUESS_MLP, "cold": B.SRMHD_GUESS_COLD}
+_GUESS = {"prev": B.SRMHD_GUESS_PREV, "mlp": B.SRMHD_GUESS_MLP, "cold": B.SRMHD_GUESS_COLD,
+          "mlp_all": B.SRMHD_GUESS_MLP_ALL}
 _REC = {"mp5": B.SRMHD_REC_MP5, "mc": B.SRMHD_REC_MC}
 
 

@@ -355,7 +355,10 @@ def test_kernel_timing_counts_launches():
     S.kernel_timing(True)
     S.step(2)
     kt = S.kernel_times()
-    assert kt["c2p"][1] == 6 and kt["flux_x"][1] == 6 and kt["update"][1] == 6 and kt["dt"][1] == 2
+    # stages 1 and 2 invert their output inside the update: one separate
+    # inversion and one plain update per step
+    assert kt["c2p"][1] == 2 and kt["update_c2p"][1] == 4 and kt["update"][1] == 2
+    assert kt["flux_x"][1] == 6 and kt["dt"][1] == 2
     assert kt["uct_x"][1] == 6 and kt["uct_y"][1] == 6 and kt["uct_z"][1] == 6
     assert all(v[0] > 0 for v in kt.values())
     S.close()
@@ -436,3 +439,41 @@ def test_set_state_without_w_starts_cold():
     assert cold > warm
     np.testing.assert_allclose(Pb, Pa, rtol=1e-12, atol=1e-12)
     A.close()
+
+
+# ------------------------------------------- update fused with the inversion
+@pytest.mark.parametrize("kw,fused", [({}, True), ({"precision": "mixed"}, True),
+                                      ({"guess": "cold"}, True),
+                                      ({"recon": "mc", "time_order": 2}, True),
+                                      ({"high_order": True}, False)])
+def test_fused_update_inversion(kw, fused):
+    """Periodic boxes without HO invert the output of a step's first stages
+    inside their update (k_update_c2p): one separate inversion per step (at
+    its first stage), and the state matches the oracle at the plain parity
+    bar (FP64).  (That the fused path gives the bits of separate inversions
+    is shown by the z-slab tests, whose slab contexts invert separately.)"""
+    n, steps = 24, 3
+    prim5, bf, _ = I.cpa(n, diagonal=True)
+    S = _solver((n, n, n), **kw)
+    S.init(prim5, bf)
+    S.kernel_timing(True)
+    S.step(steps)
+    kt = S.kernel_times()
+    S.kernel_timing(False)
+    nst = 2 if kw.get("time_order", 3) == 2 else 3
+    if fused:
+        assert kt["c2p"][1] == steps and kt["update_c2p"][1] == (nst - 1) * steps
+        assert kt["update"][1] == steps
+    else:
+        assert kt["c2p"][1] == nst * steps and kt["update_c2p"][1] == 0
+    torch.cuda.synchronize()
+    if kw.get("precision", "fp64") == "fp64":
+        g = _oracle((n, n, n), recon=1 if kw.get("recon") == "mc" else 0,
+                    time_order=kw.get("time_order", 3), ho=1 if kw.get("high_order") else 0)
+        cons, W = g.init(prim5, bf)
+        bfo = [b.copy() for b in bf]
+        g.step(cons, bfo, W, steps)
+        got = [a.cpu().numpy() for a in S.cons] + [b.cpu().numpy() for b in S.bface]
+        for q, (a, r) in enumerate(zip(got, list(cons) + bfo)):
+            assert l1rel(a, r, 1.0) <= 1e-12, q
+    S.close()
