@@ -89,9 +89,10 @@ KERNEL_UNITS = {
 # the plain update in stage 3 only (when stages 1 and 2 run fused)
 KERNEL_UNITS_FUSED_UPDATE = (336.0, 276.0, 80.0)
 # rocprofv3 kernel names of each class's FP64 launches in one step (name,
-# launches per step), for the HBM traffic read from the profiles
+# launches per step), for the HBM traffic read from the profiles (the mixed
+# form's names have float for double)
 PROFILED_KERNEL = {
-    "c2p": [("k_c2p<false, false>", 3)],
+    "c2p": [("k_c2p<false, false, false>", 1)],
     "flux_x": [("k_flux<0, double, false, false, 0, true>", 3)],
     "flux_y": [("k_flux<1, double, false, false, 0, true>", 3)],
     "flux_z": [("k_flux<2, double, true, false, 0, true>", 1),
@@ -99,10 +100,8 @@ PROFILED_KERNEL = {
     "uct_x": [("k_uct<0, double, 0, true>", 3)],
     "uct_y": [("k_uct<1, double, 0, true>", 3)],
     "uct_z": [("k_uct<2, double, 0, true>", 3)],
-    "update": [("k_update<1, double>", 1), ("k_update<2, double>", 1),
-               ("k_update<3, double>", 1)],
-    "update_c2p": [("k_update_c2p<1, double, false>", 1), ("k_update_c2p<2, double, false>", 1),
-                   ("k_update_c2p<3, double, false>", 1)],
+    "update": [("k_update<3, double>", 1)],
+    "update_c2p": [("k_update_c2p<1, double, false>", 1), ("k_update_c2p<2, double, false>", 1)],
 }
 
 
@@ -118,16 +117,18 @@ def kernel_sources_sha():
     return h.hexdigest()[:16]
 
 
-def profiled_traffic(kernel_cls):
-    """HBM bytes per launch of class `kernel_cls`, averaged over its launches
-    in one step, from the committed rocprofv3 summaries (FETCH_SIZE and
-    WRITE_SIZE scaled by a plain copy's readings), or None when the kernel
-    sources changed since the counters were taken."""
+def profiled_traffic(kernel_cls, workload):
+    """Bytes per launch of class `kernel_cls` leaving the L2 (HBM or the
+    memory-side cache), averaged over its launches in one step, from the
+    committed rocprofv3 summary of `workload` (e.g. "cpa512 fp64"): FETCH_SIZE
+    and WRITE_SIZE scaled by a plain copy's readings, the reads cross-checked
+    against the 128/64/32-byte request counts; None when there is no such
+    summary or the kernel sources changed since the counters were taken."""
     import glob
     sha = kernel_sources_sha()
     for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.txt"))):
         txt = open(f).read()
-        if f"kernel sources sha256[:16]: {sha}" not in txt:
+        if f"kernel sources sha256[:16]: {sha}" not in txt or f"workload: {workload}\n" not in txt:
             continue
         got = {}
         for line in txt.splitlines():
@@ -135,6 +136,8 @@ def profiled_traffic(kernel_cls):
                 name, val = line[len("traffic_bytes_per_launch "):].rsplit(":", 1)
                 got[name.strip()] = int(val)
         parts = PROFILED_KERNEL[kernel_cls]
+        if workload.endswith("mixed"):
+            parts = [(k.replace("double", "float"), w) for k, w in parts]
         if all(k in got for k, _ in parts):
             return int(sum(got[k] * w for k, w in parts) / sum(w for _, w in parts))
     return None
@@ -466,8 +469,8 @@ def main():
                     "unit": "TFLOP/s", "frac": round(tfl / fpeak, 4), "traffic": None}
         default_scheme = (not args.high_order and args.recon == "mp5" and args.time_order == 3
                           and args.guess == "prev")
-        if args.precision == "fp64" and n == 256 and default_scheme:
-            roof["traffic"] = profiled_traffic(dom)
+        if default_scheme:
+            roof["traffic"] = profiled_traffic(dom, f"cpa{n} {args.precision}")
         roof.update({"kernel": dom, "avg_ms": round(kernels[dom]["avg_ms"], 4),
                      "alg_bytes_per_launch": bytes_per, "state_bytes_per_cell": sb,
                      "alg_flops_per_launch": flops_per,
