@@ -19,11 +19,13 @@ def test_kernel_units_and_profile_lookup():
     kernel sources changed since it was taken)."""
     sys.path.insert(0, ROOT)
     import bench
-    assert set(bench.PROFILED_KERNEL) == set(bench.KERNEL_UNITS)
+    assert set(bench.PROFILED_KERNEL) == set(bench.KERNEL_UNITS) == set(bench.STATE_BYTES)
     for cls, (b64, bmx, fl) in bench.KERNEL_UNITS.items():
         assert b64 > bmx > 0 and fl > 0
-        t = bench.profiled_traffic(cls)
-        assert t is None or t > 0.5 * b64 * 256 ** 3
+        assert 0 < bench.STATE_BYTES[cls] <= b64
+        for prec in ("fp64", "mixed"):
+            t = bench.profiled_traffic(cls, f"cpa512 {prec}")
+            assert t is None or t > 0.3 * (b64 if prec == "fp64" else bmx) * 512 ** 3
 
 
 def test_workload_label_names_the_timed_scheme():
