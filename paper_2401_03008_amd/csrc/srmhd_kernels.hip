@@ -691,7 +691,7 @@ __global__ __launch_bounds__((FluxTile<DIR, TS, STAGED>::kThreads)) void k_flux(
     const T sum = ap + am;
     T F[5];
     if (sum > T(0)) {
-      const T inv = T(1) / sum, apam = ap * am;
+      const T inv = recip(sum), apam = ap * am;
 #pragma unroll
       for (int n = 0; n < 5; ++n) F[n] = (ap * eL.f[n] + am * eR.f[n] - apam * (eR.u[n] - eL.u[n])) * inv;
     } else {

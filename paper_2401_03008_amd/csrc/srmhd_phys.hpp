@@ -34,6 +34,20 @@ struct FaceEval {
 template <typename T>
 __device__ __forceinline__ T sq(T a) { return a * a; }
 
+// 1/x for the face-physics and edge-formula denominators (finite, positive,
+// of moderate size: no zero, infinity or denormal handling).  FP64: the
+// hardware reciprocal estimate refined by two Newton-Raphson steps for
+// f(r) = 1/r - x, r <- r + r (1 - x r), each of which squares the relative
+// error; FP32: the hardware reciprocal (within 1 ulp).
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+
 // Sec. 2 conserved variables and normal fluxes; fast speeds from the quadratic
 // bound of Del Zanna et al. (2003): w^2 = c_s^2 + v_A^2 - c_s^2 v_A^2 with
 // c_s^2 = g p/(rho h), v_A^2 = b^2/(rho h + b^2), b^2 = B^2/Gamma^2 + (v.B)^2.
@@ -53,7 +67,7 @@ __device__ __forceinline__ void face_eval(const FaceState<T>& s, T g, T g1,
   const T b2 = B2 * one_m_v2 + vB * vB;  // comoving field strength squared
   // one division for 1/(1 - v^2), 1/(rho h) and 1/(rho h + b^2)
   const T q1 = rhoh * (rhoh + b2);
-  const T r = T(1) / (one_m_v2 * q1);
+  const T r = recip(one_m_v2 * q1);
   const T lor2 = q1 * r;                       // 1/(1 - v^2)
   const T inv_rhoh = one_m_v2 * (rhoh + b2) * r;
   const T inv_rhohb = one_m_v2 * rhoh * r;
@@ -77,7 +91,7 @@ __device__ __forceinline__ void face_eval(const FaceState<T>& s, T g, T g1,
   const T va2 = b2 * inv_rhohb;
   const T w2 = cs2 + va2 - cs2 * va2;
   const T den = T(1) - v2 * w2;
-  const T inv_den = T(1) / den;
+  const T inv_den = recip(den);
   T disc = w2 * one_m_v2 * (den - s.vn * s.vn * (T(1) - w2));
   disc = disc > T(0) ? disc : T(0);
   const T sqd = sqrt(disc);
@@ -212,7 +226,7 @@ __device__ __forceinline__ T uct_edge(T ELL, T ELR, T ERL, T ERR, T app, T apm,
   const T sp = app + apm, sq_ = aqp + aqm;
   if (sp > T(0) && sq_ > T(0)) {
     // one reciprocal for the weights and both dissipation coefficients
-    const T inv = T(1) / (sp * sq_);
+    const T inv = recip(sp * sq_);
     const T e = (app * aqp * ELL + app * aqm * ELR + apm * aqp * ERL + apm * aqm * ERR) * inv;
     const T dp = app * apm * sq_ * inv;
     const T dq = aqp * aqm * sp * inv;
