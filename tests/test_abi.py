@@ -115,3 +115,91 @@ def test_stale_library_rejected(L, tmp_path):
     assert source_id(str(tmp_path)) != source_id()
     with pytest.raises(RuntimeError, match="other sources"):
         B.check_build_id(L, str(tmp_path))
+
+
+def test_struct_layouts_match_the_header(L, tmp_path):
+    """The ctypes mirrors of srmhd_config, srmhd_buffers and srmhd_diag have
+    the C structs' sizes and field offsets (a C program compiled against
+    include/srmhd.h prints them)."""
+    import subprocess
+    fields = {"srmhd_config": B.Config, "srmhd_buffers": B.Buffers, "srmhd_diag": B.Diag}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "srmhd.h"', "int main(void) {"]
+    for cname, py in fields.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(B.HEADER))
+    subprocess.run(["gcc", "-I", inc, "-o", str(exe), str(src)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout
+    got = {}
+    for line in out.splitlines():
+        name, f, v = line.split()
+        got[(name, f)] = int(v)
+    for cname, py in fields.items():
+        assert got[(cname, "size")] == C.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
+
+
+def test_header_constants_match_the_binding():
+    import re
+    txt = open(B.HEADER).read()
+    defs = dict(re.findall(r"#define (SRMHD_\w+) \(?(-?\w+)\)?", txt))
+    assert int(defs["SRMHD_NKCLASS"]) == B.NKCLASS == len(B.KCLASS_NAMES)
+    assert int(defs["SRMHD_MLP_NPARAM"]) == B.MLP_NPARAM
+    assert int(defs["SRMHD_MLP_NOALLOC_MAX_BATCH"]) == B.MLP_NOALLOC_MAX_BATCH
+    for k, v in B.MLP_OFF.items():
+        assert int(defs["SRMHD_MLP_OFF_" + k.upper()]) == v
+    for code in ("OK", "E_INVAL", "E_HIP", "E_C2P", "E_NONFINITE", "E_STATE"):
+        assert int(defs["SRMHD_" + code]) == getattr(B, "SRMHD_" + code)
+    enums = dict(re.findall(r"(SRMHD_GUESS_\w+) = (\d+)", txt))
+    assert {k: int(v) for k, v in enums.items()} == {
+        "SRMHD_GUESS_PREV": B.SRMHD_GUESS_PREV, "SRMHD_GUESS_MLP": B.SRMHD_GUESS_MLP,
+        "SRMHD_GUESS_COLD": B.SRMHD_GUESS_COLD, "SRMHD_GUESS_MLP_ALL": B.SRMHD_GUESS_MLP_ALL}
+
+
+@pytest.mark.parametrize("kw", [{"ghost_z": 3}, {"ghost_z": 7, "high_order": 1},
+                                {"ghost_z": 4, "nz": 3}, {"ghost_z": 65}, {"ghost_z": -1}])
+def test_invalid_slab_configs_rejected(L, kw):
+    cfg = B.srmhd_config_default()
+    for k, v in kw.items():
+        setattr(cfg, k, v)
+    with pytest.raises(B.SrmhdError) as e:
+        B.srmhd_work_bytes(cfg)
+    assert e.value.code == B.SRMHD_E_INVAL and "ghost" in B.srmhd_last_error(None)
+
+
+def test_slab_work_covers_the_ghost_planes(L):
+    cfg = B.srmhd_config_default()
+    cfg.nz, cfg.ghost_z = 16, 4
+    w = B.srmhd_work_bytes(cfg)
+    cfg2 = B.srmhd_config_default()
+    cfg2.nz = 24
+    assert w == B.srmhd_work_bytes(cfg2)
+
+
+def test_null_context_stage_and_halo_calls(L):
+    n = C.c_size_t()
+    assert L.srmhd_stage_begin(None, 1) == B.SRMHD_E_INVAL
+    assert L.srmhd_stage_end(None, 1, None) == B.SRMHD_E_INVAL
+    assert L.srmhd_local_amax(None, None) == B.SRMHD_E_INVAL
+    assert L.srmhd_halo_count(None, C.byref(n)) == B.SRMHD_E_INVAL
+    assert L.srmhd_halo_pack(None, 0, None) == B.SRMHD_E_INVAL
+    assert L.srmhd_halo_unpack(None, 0, None) == B.SRMHD_E_INVAL
+
+
+def test_noalloc_forward_checks_before_any_launch(L):
+    """Batch limits and null pointers are refused on the host (no device call:
+    this runs without a GPU)."""
+    p = 256
+    for batch in (0, B.MLP_NOALLOC_MAX_BATCH + 1):
+        rc = L.srmhd_mlp_forward_noalloc(C.c_void_p(p), C.c_void_p(p), C.c_void_p(p),
+                                         C.c_void_p(p), batch, None)
+        assert rc == B.SRMHD_E_INVAL
+        assert "65536" in B.srmhd_last_error(None)
+    rc = L.srmhd_mlp_forward_noalloc(None, C.c_void_p(p), C.c_void_p(p), C.c_void_p(p), 8, None)
+    assert rc == B.SRMHD_E_INVAL
