@@ -404,7 +404,7 @@ def main():
                time_order=args.time_order, high_order=args.high_order)
     S.init(prim5, bf)
     del prim5, bf
-    if args.guess == "mlp":
+    if args.guess in ("mlp", "mlp_all"):
         from paper_2401_03008_amd.learned import train_default
         net = train_default()[0]
         S.set_mlp(net)
