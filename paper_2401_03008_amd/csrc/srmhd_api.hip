@@ -41,6 +41,7 @@ struct srmhd_ctx {
   double* ureg2b[3];  // face B of U2 (stage 2 must not overwrite U1's B in place)
   double* prim64[8];
   float* prim32[8];
+  float* bf32[3];  // mixed form: FP32 copies of the stage's face B (REC operands)
   void* fhat[3][5];
   void* apm[3][2];
   void* fv[3][4];
@@ -181,10 +182,10 @@ Layout layout_of(const srmhd_config* c) {
   L.arr_bytes32 = align_up(n * sizeof(float));
   const bool mixed = c->precision == SRMHD_MIXED;
   // RK register (8 + 3 for U2's face B) + edge E (3) always FP64; prims FP64
-  // (8) or FP32 (8); faces
-  // (15 fluxes + 6 speeds + 12 velocity states) in the flux precision.
+  // (8) or FP32 (8, plus FP32 copies of the 3 face B); faces (15 fluxes + 6
+  // speeds + 12 velocity states) in the flux precision.
   L.n64 = 8 + 3 + 3 + (mixed ? 0 : 8 + 33);
-  L.n32 = mixed ? 8 + 33 : 0;
+  L.n32 = mixed ? 8 + 3 + 33 : 0;
   L.total = L.off_arr + L.n64 * L.arr_bytes64 + L.n32 * L.arr_bytes32;
   return L;
 }
@@ -219,7 +220,7 @@ void stage_flux(srmhd_ctx* c, const StageState& st, bool cfl) {
     a.g = c->g;
     for (int n = 0; n < 8; ++n)
       a.prim[n] = c->mixed ? (const TS*)c->prim32[n] : (const TS*)c->prim64[n];
-    a.bn = st.bf[d];
+    a.bn = c->mixed ? (const TS*)c->bf32[d] : (const TS*)st.bf[d];
     for (int n = 0; n < 5; ++n) a.fhat[n] = (TS*)c->fhat[d][n];
     a.ap = (TS*)c->apm[d][0];
     a.am = (TS*)c->apm[d][1];
@@ -252,7 +253,7 @@ void stage_uct_update(srmhd_ctx* c, const StageState& st, int stage, double* con
       for (int n = 0; n < 4; ++n) a.fv[d][n] = (const TS*)c->fv[d][n];
       a.ap[d] = (const TS*)c->apm[d][0];
       a.am[d] = (const TS*)c->apm[d][1];
-      a.bf[d] = st.bf[d];
+      a.bf[d] = c->mixed ? (const TS*)c->bf32[d] : (const TS*)st.bf[d];
       a.e[d] = c->edge[d];
     }
     for (int k = 0; k < 3; ++k) {
@@ -299,6 +300,8 @@ C2PArgs c2p_args(srmhd_ctx* c, const StageState& st, double* const* prim64, floa
     a.prim64[n] = prim64 ? prim64[n] : nullptr;
     a.prim32[n] = prim32 ? prim32[n] : nullptr;
   }
+  // the FP32 face B for the mixed form's REC, with the stage's FP32 primitives
+  for (int d = 0; d < 3; ++d) a.bf32[d] = prim32 ? c->bf32[d] : nullptr;
   a.gam = c->cfg.gamma_ad;
   a.tol = c->cfg.newton_tol;
   a.pfloor = c->cfg.pfloor;
@@ -515,6 +518,7 @@ int srmhd_create(const srmhd_config* cfg, const srmhd_buffers* buf, void* stream
     c->prim64[n] = c->mixed ? nullptr : take64();
     c->prim32[n] = c->mixed ? take32() : nullptr;
   }
+  for (int d = 0; d < 3; ++d) c->bf32[d] = c->mixed ? take32() : nullptr;
   for (int d = 0; d < 3; ++d) {
     for (int n = 0; n < 5; ++n) c->fhat[d][n] = takeT();
     for (int n = 0; n < 2; ++n) c->apm[d][n] = takeT();

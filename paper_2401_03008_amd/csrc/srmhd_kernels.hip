@@ -466,6 +466,8 @@ __global__ __launch_bounds__(kThreads) void k_c2p(C2PArgs a) {
       for (int n = 0; n < 5; ++n) a.prim32[n][c.id] = (float)pr[n];
       for (int d = 0; d < 3; ++d) a.prim32[5 + d][c.id] = (float)b[d];
     }
+    if (a.bf32[0])
+      for (int d = 0; d < 3; ++d) a.bf32[d][c.id] = (float)a.bf[d][c.id];
     if (rc != 0 && c.k >= a.g.zplo && c.k < a.g.zphi) {
       const unsigned bit = rc == 1 ? kErrC2P : (rc == 2 ? kErrNonfinite : kErrPressure);
       atomicOr(a.err, bit);
@@ -1033,6 +1035,8 @@ __global__ __launch_bounds__(kThreads) void k_update_c2p(UpdArgs<TS> a, C2PArgs 
       for (int n = 0; n < 5; ++n) p.prim32[n][c.id] = (float)pr[n];
       for (int d = 0; d < 3; ++d) p.prim32[5 + d][c.id] = (float)b[d];
     }
+    if (p.bf32[0])
+      for (int d = 0; d < 3; ++d) p.bf32[d][c.id] = (float)un[5 + d];
     if (rc != 0) {
       const unsigned bit = rc == 1 ? kErrC2P : (rc == 2 ? kErrNonfinite : kErrPressure);
       atomicOr(p.err, bit);

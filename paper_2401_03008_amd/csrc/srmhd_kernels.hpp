@@ -68,6 +68,7 @@ struct C2PArgs {
   double* W;
   double* prim64[8];  // FP64 outputs (or null)
   float* prim32[8];   // FP32 copies for the mixed form (or null)
+  float* bf32[3];     // mixed form: FP32 copies of the face B (or null)
   double gam, tol, pfloor;
   int maxit;
   int guess;  // 0 = previous W, 1 = learned guess (fallback previous W), 2 = cold start
@@ -104,7 +105,7 @@ template <typename TS>
 struct FluxArgs {
   GridDims g;
   const TS* prim[8];   // rho, vx, vy, vz, p, Bcx, Bcy, Bcz
-  const double* bn;    // face-normal B of this direction
+  const TS* bn;        // face-normal B of this direction (FP32 copy in the mixed form)
   TS* fhat[5];         // D, Sx, Sy, Sz, U fluxes at the +face
   TS* ap;
   TS* am;
@@ -125,7 +126,7 @@ struct Uct3Args {
   const TS* fv[3][4];  // per face direction d: left v_d, v_{d+1}; right v_d, v_{d+1}
   const TS* ap[3];
   const TS* am[3];
-  const double* bf[3];
+  const TS* bf[3];  // face B (FP32 copies in the mixed form)
   double* e[3];
 };
 
