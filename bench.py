@@ -2,7 +2,7 @@
 """Throughput of the SSP-RK3 SRMHD step on one MI355X.
 
 Workload: the circularly polarised Alfven wave on the box diagonal,
-k = 2 pi (1,1,1), 256^3 cells, rho = p = B0 = eta = 1, gamma 4/3, CFL 0.5,
+k = 2 pi (1,1,1), 512^3 cells (--n), rho = p = B0 = eta = 1, gamma 4/3, CFL 0.5,
 plain FP64 state (5 conserved + 3 staggered B + Newton guess W), MP5 + HLL +
 UCT + SSP-RK3.  A step is one full RK3 step (3 stages) over the whole box;
 the metric is cell updates per second (N^3 steps / s).
@@ -16,6 +16,10 @@ Prints one JSON line.  Besides the contract keys it carries:
                 -- the measured bandwidth of a plain 2 GiB device copy, and the
                    step-level HBM fraction (state bytes per cell-step x rate)
                    against it as well as against the 8 TB/s peak;
+  copy_floor    -- the bytes every kernel of a step must move, intermediates
+                   included (the per-unit figures below times each class's
+                   launches), the time a plain copy would take to move them,
+                   and that time over the measured step;
   cpu_baseline  -- the FP64 CPU oracle timed on this host on a bounded sample
                    (the same wave at 64^3, a few steps, all cores; then one
                    thread);
@@ -141,6 +145,20 @@ def profiled_traffic(kernel_cls, workload):
         if all(k in got for k, _ in parts):
             return int(sum(got[k] * w for k, w in parts) / sum(w for _, w in parts))
     return None
+
+
+def step_bytes_with_intermediates(kernels, steps, precision):
+    """Bytes per cell and step that the timed kernels must move, intermediates
+    included: each class's per-unit bytes (KERNEL_UNITS) times its launches
+    per step.  `kernels`: {class: {"launches": ...}} over `steps` steps."""
+    col = 1 if precision == "mixed" else 0
+    fused = "update_c2p" in kernels
+    total = 0.0
+    for k, v in kernels.items():
+        if k in KERNEL_UNITS:
+            u = KERNEL_UNITS_FUSED_UPDATE if (fused and k == "update") else KERNEL_UNITS[k]
+            total += u[col] * v["launches"] / steps
+    return total
 
 
 def stream_copy_gbs(gib=2, reps=5):
@@ -435,6 +453,7 @@ def main():
           file=sys.stderr, flush=True)
 
     roof = None
+    floor = None
     kernels = {}
     if not args.no_kernel_timing:
         S.kernel_timing(True)
@@ -478,10 +497,17 @@ def main():
                      "bytes_with_intermediates_per_launch": bytes_with_inter,
                      "achieved_with_intermediates_gbs": round(gbs_inter, 1),
                      "frac_with_intermediates": round(gbs_inter / HBM_PEAK_GBS, 4)})
+        if default_scheme:
+            floor = {"bytes_per_cell_step":
+                     round(step_bytes_with_intermediates(kernels, args.steps, args.precision), 1)}
         print(f"[bench] kernel timing: {json.dumps(kernels)}", file=sys.stderr, flush=True)
     S.close()
     copy_gbs = stream_copy_gbs()
     print(f"[bench] plain device copy: {copy_gbs:.0f} GB/s", file=sys.stderr, flush=True)
+    if floor is not None:
+        fms = floor["bytes_per_cell_step"] * n ** 3 / (copy_gbs * 1e9) * 1e3
+        floor.update({"copy_ms_per_step": round(fms, 3),
+                      "frac_of_step": round(fms / ms_per_step, 4)})
 
     forms = None
     if not args.no_forms:
@@ -539,6 +565,7 @@ def main():
         "stream_copy_gbs": round(copy_gbs, 1),
         "hbm_roofline_frac_step_vs_copy": round(value * 1e6 * step_bytes / (copy_gbs * 1e9), 4),
         "roofline": roof,
+        "copy_floor": floor,
         "cpu_baseline": cpu,
         "kernels": kernels,
         "forms": forms,

@@ -939,123 +939,180 @@ __device__ __forceinline__ double curl_face(double a0, double a1, double ia, dou
   return -__builtin_fma(a0 - a1, ia, -((b0 - b1) * ib));
 }
 
-// Second-order DER of cell c: one-sided differences of the +face fluxes and
-// the edge fields into r[8].
+// The plain update kernels march each thread along z over kUpdZ planes of
+// its (i, j) column (64 x 4 x kUpdZ cells per workgroup): the -z face fluxes
+// and the edge fields of the plane below are the ones the thread read as the
+// +z values of its previous plane, so each plane reads them once instead of
+// twice.  The sums are formed in the same order as with one cell per thread.
+constexpr int kUpdZ = 8;
+
+// Second-order DER of the five conserved variables: -sum_d (F(+d face) -
+// F(-d face)) / dx_d over d = 0, 1, 2 in that order, with the -z fluxes from
+// fzm (updated to this plane's +z fluxes).
 template <typename TS>
-__device__ __forceinline__ void der2(const UpdArgs<TS>& a, const Cell& c, int im, int jm, int km,
-                                     double* r) {
+__device__ __forceinline__ void der2_fluid(const UpdArgs<TS>& a, int id, int im, int jm,
+                                           double* fzm, double* r) {
   const double* ix = a.g.inv_dx;
-  const double* Ex = a.e[0];
-  const double* Ey = a.e[1];
-  const double* Ez = a.e[2];
-  const int nb[3] = {im, jm, km};
 #pragma unroll
   for (int n = 0; n < 5; ++n) {
     double acc = 0.0;
-#pragma unroll
-    for (int d = 0; d < 3; ++d)
-      acc = __builtin_fma((double)a.fhat[d][n][c.id] - (double)a.fhat[d][n][nb[d]], ix[d], acc);
+    acc = __builtin_fma((double)a.fhat[0][n][id] - (double)a.fhat[0][n][im], ix[0], acc);
+    acc = __builtin_fma((double)a.fhat[1][n][id] - (double)a.fhat[1][n][jm], ix[1], acc);
+    const double fz = (double)a.fhat[2][n][id];
+    acc = __builtin_fma(fz - fzm[n], ix[2], acc);
+    fzm[n] = fz;
     r[n] = -acc;
   }
-  const double ex0 = Ex[c.id], ey0 = Ey[c.id], ez0 = Ez[c.id];
-  r[5] = curl_face(ez0, Ez[jm], ix[1], ey0, Ey[km], ix[2]);
-  r[6] = curl_face(ex0, Ex[km], ix[2], ez0, Ez[im], ix[0]);
-  r[7] = curl_face(ey0, Ey[im], ix[0], ex0, Ex[jm], ix[1]);
 }
 
 template <int STAGE, typename TS>
 __global__ __launch_bounds__(kThreads) void k_update(UpdArgs<TS> a) {
-  const Cell c = cell_of_tile<kBlockY, 1>(a.g);
-  if (!c.valid) return;
-  double r[8];
-  der2(a, c, minus1(a.g, c, 0), minus1(a.g, c, 1), minus1(a.g, c, 2), r);
-  rk_apply<STAGE>(a, c, r);
+  const Cell c0 = cell_of_tile<kBlockY, kUpdZ>(a.g);
+  if (!c0.valid) return;
+  const GridDims& g = a.g;
+  const int plane = g.nx * g.ny;
+  const int di = c0.i == 0 ? g.nx - 1 : -1;
+  const int dj = c0.j == 0 ? (g.ny - 1) * g.nx : -g.nx;
+  const double* ix = g.inv_dx;
+  const double* Ex = a.e[0];
+  const double* Ey = a.e[1];
+  const double* Ez = a.e[2];
+  int id = c0.id;
+  const int km = c0.k == 0 ? id + (g.nz - 1) * plane : id - plane;
+  double fzm[5];
+#pragma unroll
+  for (int n = 0; n < 5; ++n) fzm[n] = (double)a.fhat[2][n][km];
+  double exm = Ex[km], eym = Ey[km];  // E_x, E_y of the plane below
+  const int kend = min(c0.k + kUpdZ, g.nz);
+  for (int k = c0.k; k < kend; ++k, id += plane) {
+    const int im = id + di, jm = id + dj;
+    double r[8];
+    der2_fluid(a, id, im, jm, fzm, r);
+    const double ex0 = Ex[id], ey0 = Ey[id], ez0 = Ez[id];
+    r[5] = curl_face(ez0, Ez[jm], ix[1], ey0, eym, ix[2]);
+    r[6] = curl_face(ex0, exm, ix[2], ez0, Ez[im], ix[0]);
+    r[7] = curl_face(ey0, Ey[im], ix[0], ex0, Ex[jm], ix[1]);
+    exm = ex0;
+    eym = ey0;
+    Cell c = c0;
+    c.id = id;
+    rk_apply<STAGE>(a, c, r);
+  }
 }
 
 // The update of stage STAGE (1 or 2: not the step's last) fused with the
 // inversion of its result (the next stage's INT + Newton, as k_c2p with guess
 // 0 or 2), for periodic boxes with the face-average INT: the updated state
 // never leaves the registers before the inversion reads it.  The face average
-// needs the updated B of the three minus faces; each cell re-derives them
-// with the same curl and the same combination as the neighbour that stores
-// them, so the centred B is the one k_c2p would read back.  That re-reads the
-// neighbours' input B, so the face-B output must not alias the stage's input
-// B (stage 2 writes it to its own register).  p carries the inversion's
-// outputs (primitives, W) and settings.
+// needs the updated B of the three minus faces: B_z at k-1 is the one the
+// thread computed on its previous plane; B_x at i-1 and B_y at j-1 (and B_z
+// at the first plane) are re-derived with the same curl and the same
+// combination as the neighbour that stores them, so the centred B is the one
+// k_c2p would read back.  That re-reads the neighbours' input B, so the
+// face-B output must not alias the stage's input B (stage 2 writes it to its
+// own register).  p carries the inversion's outputs (primitives, W) and
+// settings.
 template <int STAGE, typename TS, bool STATS>
 __global__ __launch_bounds__(kThreads) void k_update_c2p(UpdArgs<TS> a, C2PArgs p) {
   __shared__ unsigned s_cnt[CNT_N];
   BlockCounters bc;
   if (STATS) bc.init(s_cnt);
-  const Cell c = cell_of_tile<kBlockY, 1>(a.g);
-  int iters = 0, rc = 0;
-  bool floored = false;
-  if (c.valid) {
-    const GridDims& g = a.g;
-    const int i1 = c.i == 0 ? g.nx - 1 : c.i - 1;
-    const int j1 = c.j == 0 ? g.ny - 1 : c.j - 1;
-    const int k1 = c.k == 0 ? g.nz - 1 : c.k - 1;
-    auto at = [&](int i, int j, int k) { return (k * g.ny + j) * g.nx + i; };
-    const int im = at(i1, c.j, c.k), jm = at(c.i, j1, c.k), km = at(c.i, c.j, k1);
-    double r[8];
-    der2(a, c, im, jm, km, r);
-    const double dt = a.sc->dt;
-    double un[8];
+  const Cell c0 = cell_of_tile<kBlockY, kUpdZ>(a.g);
+  const GridDims& g = a.g;
+  // every lane of a workgroup runs the same planes (the counters are
+  // wavefront-wide); lanes past a ragged x or y edge do no work
+  const bool lane_ok = c0.i < g.nx && c0.j < g.ny;
+  const int i1 = c0.i == 0 ? g.nx - 1 : c0.i - 1;
+  const int j1 = c0.j == 0 ? g.ny - 1 : c0.j - 1;
+  const double* ix = g.inv_dx;
+  const double* Ex = a.e[0];
+  const double* Ey = a.e[1];
+  const double* Ez = a.e[2];
+  const double dt = a.sc->dt;
+  auto at = [&](int i, int j, int k) { return (k * g.ny + j) * g.nx + i; };
+  // carried from the plane below: its +z face fluxes, E_x and E_y at (i, j),
+  // E_x at (i, j-1), E_y at (i-1, j), and its updated B_z
+  double fzm[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  double exm = 0.0, eym = 0.0, exjm = 0.0, eyim = 0.0, bzm = 0.0;
+  const int k0 = c0.k;
+  const int kend = min(k0 + kUpdZ, g.nz);
+  if (lane_ok && k0 < g.nz) {
+    const int k1 = k0 == 0 ? g.nz - 1 : k0 - 1;
+    const int km = at(c0.i, c0.j, k1), imkm = at(i1, c0.j, k1), jmkm = at(c0.i, j1, k1);
 #pragma unroll
-    for (int n = 0; n < 8; ++n) {
-      un[n] = rk_combine<STAGE>(STAGE == 1 ? 0.0 : a.u0[n][c.id], a.ucur[n][c.id], dt, r[n]);
-      a.uout[n][c.id] = un[n];
-    }
-    // the updated minus-face B: B_x at i-1, B_y at j-1, B_z at k-1
-    const int imjm = at(i1, j1, c.k), imkm = at(i1, c.j, k1), jmkm = at(c.i, j1, k1);
-    const double* ix = g.inv_dx;
-    const double* Ex = a.e[0];
-    const double* Ey = a.e[1];
-    const double* Ez = a.e[2];
-    const double rm[3] = {curl_face(Ez[im], Ez[imjm], ix[1], Ey[im], Ey[imkm], ix[2]),
-                          curl_face(Ex[jm], Ex[jmkm], ix[2], Ez[jm], Ez[imjm], ix[0]),
-                          curl_face(Ey[km], Ey[imkm], ix[0], Ex[km], Ex[jmkm], ix[1])};
-    const int nm[3] = {im, jm, km};
-    double b[3];
+    for (int n = 0; n < 5; ++n) fzm[n] = (double)a.fhat[2][n][km];
+    exm = Ex[km];
+    eym = Ey[km];
+    exjm = Ex[jmkm];
+    eyim = Ey[imkm];
+    bzm = rk_combine<STAGE>(STAGE == 1 ? 0.0 : a.u0[7][km], a.ucur[7][km], dt,
+                            curl_face(eym, eyim, ix[0], exm, exjm, ix[1]));
+  }
+  for (int k = k0; k < kend; ++k) {
+    int iters = 0, rc = 0;
+    bool floored = false;
+    if (lane_ok) {
+      const int id = at(c0.i, c0.j, k), im = at(i1, c0.j, k), jm = at(c0.i, j1, k);
+      const int imjm = at(i1, j1, k);
+      double r[8];
+      der2_fluid(a, id, im, jm, fzm, r);
+      const double ex0 = Ex[id], ey0 = Ey[id], ez0 = Ez[id];
+      const double exj = Ex[jm], eyi = Ey[im], ezi = Ez[im], ezj = Ez[jm];
+      r[5] = curl_face(ez0, ezj, ix[1], ey0, eym, ix[2]);
+      r[6] = curl_face(ex0, exm, ix[2], ez0, ezi, ix[0]);
+      r[7] = curl_face(ey0, eyi, ix[0], ex0, exj, ix[1]);
+      double un[8];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      const double bm = rk_combine<STAGE>(STAGE == 1 ? 0.0 : a.u0[5 + d][nm[d]],
-                                          a.ucur[5 + d][nm[d]], dt, rm[d]);
-      b[d] = 0.5 * (bm + un[5 + d]);
+      for (int n = 0; n < 8; ++n) {
+        un[n] = rk_combine<STAGE>(STAGE == 1 ? 0.0 : a.u0[n][id], a.ucur[n][id], dt, r[n]);
+        a.uout[n][id] = un[n];
+      }
+      // the updated B_x at i-1 and B_y at j-1, re-derived
+      const double ezimjm = Ez[imjm];
+      const double bxm = rk_combine<STAGE>(STAGE == 1 ? 0.0 : a.u0[5][im], a.ucur[5][im], dt,
+                                           curl_face(ezi, ezimjm, ix[1], eyi, eyim, ix[2]));
+      const double bym = rk_combine<STAGE>(STAGE == 1 ? 0.0 : a.u0[6][jm], a.ucur[6][jm], dt,
+                                           curl_face(exj, exjm, ix[2], ezj, ezimjm, ix[0]));
+      const double b[3] = {0.5 * (bxm + un[5]), 0.5 * (bym + un[6]), 0.5 * (bzm + un[7])};
+      exm = ex0;
+      eym = ey0;
+      exjm = exj;
+      eyim = eyi;
+      bzm = un[7];
+      double W = p.guess == 2 ? -1.0 : p.W[id];
+      double pr[5];
+      rc = con2prim(un, b[0], b[1], b[2], p.gam, W, p.maxit, p.tol, p.pfloor, pr, iters, floored);
+      p.W[id] = W;
+      if (p.prim64[0]) {
+        for (int n = 0; n < 5; ++n) p.prim64[n][id] = pr[n];
+        for (int d = 0; d < 3; ++d) p.prim64[5 + d][id] = b[d];
+      }
+      if (p.prim32[0]) {
+        for (int n = 0; n < 5; ++n) p.prim32[n][id] = (float)pr[n];
+        for (int d = 0; d < 3; ++d) p.prim32[5 + d][id] = (float)b[d];
+      }
+      if (p.bf32[0])
+        for (int d = 0; d < 3; ++d) p.bf32[d][id] = (float)un[5 + d];
+      if (rc != 0) {
+        const unsigned bit = rc == 1 ? kErrC2P : (rc == 2 ? kErrNonfinite : kErrPressure);
+        atomicOr(p.err, bit);
+      }
     }
-    double W = p.guess == 2 ? -1.0 : p.W[c.id];
-    double pr[5];
-    rc = con2prim(un, b[0], b[1], b[2], p.gam, W, p.maxit, p.tol, p.pfloor, pr, iters, floored);
-    p.W[c.id] = W;
-    if (p.prim64[0]) {
-      for (int n = 0; n < 5; ++n) p.prim64[n][c.id] = pr[n];
-      for (int d = 0; d < 3; ++d) p.prim64[5 + d][c.id] = b[d];
-    }
-    if (p.prim32[0]) {
-      for (int n = 0; n < 5; ++n) p.prim32[n][c.id] = (float)pr[n];
-      for (int d = 0; d < 3; ++d) p.prim32[5 + d][c.id] = (float)b[d];
-    }
-    if (p.bf32[0])
-      for (int d = 0; d < 3; ++d) p.bf32[d][c.id] = (float)un[5 + d];
-    if (rc != 0) {
-      const unsigned bit = rc == 1 ? kErrC2P : (rc == 2 ? kErrNonfinite : kErrPressure);
-      atomicOr(p.err, bit);
+    if (STATS) {
+      bc.add_uniform(CNT_ITERS, lane_ok ? (unsigned)iters : 0u);
+      bc.add_uniform(CNT_CALLS, lane_ok ? 1u : 0u);
+      bc.add_uniform(CNT_FAIL, (lane_ok && rc != 0) ? 1u : 0u);
+      bc.add_uniform(CNT_FLOOR, (lane_ok && floored) ? 1u : 0u);
+      bc.add_hist(CNT_HIST0, lane_ok, iters < 31 ? iters : 31);
     }
   }
-  if (STATS) {
-    bc.add_uniform(CNT_ITERS, c.valid ? (unsigned)iters : 0u);
-    bc.add_uniform(CNT_CALLS, c.valid ? 1u : 0u);
-    bc.add_uniform(CNT_FAIL, (c.valid && rc != 0) ? 1u : 0u);
-    bc.add_uniform(CNT_FLOOR, (c.valid && floored) ? 1u : 0u);
-    bc.add_hist(CNT_HIST0, c.valid, iters < 31 ? iters : 31);
-    bc.flush(p.counters);
-  }
+  if (STATS) bc.flush(p.counters);
 }
 
 template <typename TS>
 void launch_update_c2p(int stage, const UpdArgs<TS>& a, const C2PArgs& p, bool stats,
                        hipStream_t s) {
-  const dim3 grid = tile_grid<kBlockY, 1>(a.g);
+  const dim3 grid = tile_grid<kBlockY, kUpdZ>(a.g);
   const dim3 blk = tile_block<kBlockY, 1>();
 #define SRMHD_UC(ST)                                                                     \
   if (stats) hipLaunchKernelGGL((k_update_c2p<ST, TS, true>), grid, blk, 0, s, a, p);    \
@@ -1199,7 +1256,7 @@ __global__ __launch_bounds__(kBlockX * 16) void k_update_ho3(UpdArgs<TS> a) {
 
 template <typename TS>
 void launch_update(int stage, const UpdArgs<TS>& a, bool ho, hipStream_t s) {
-  const dim3 grid = tile_grid<kBlockY, 1>(a.g);
+  const dim3 grid = ho ? tile_grid<kBlockY, 1>(a.g) : tile_grid<kBlockY, kUpdZ>(a.g);
   const dim3 blk = tile_block<kBlockY, 1>();
 #define SRMHD_UPD(K, ...)                                                  \
   switch (stage) {                                                        \

@@ -3,6 +3,8 @@ import os
 import subprocess
 import sys
 
+import pytest
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
@@ -41,3 +43,25 @@ def test_workload_label_names_the_timed_scheme():
     import argparse  # noqa: F401
     src = open(os.path.join(ROOT, "bench.py")).read()
     assert 'ap.add_argument("--n", type=int, default=512)' in src
+
+
+def test_step_bytes_with_intermediates():
+    """The bytes a step's kernels must move (intermediates included), from the
+    launch counts of one SSP-RK3 step with the fused update: 1 inversion,
+    3 x 3 flux passes, 3 x 3 UCT orientations, 2 fused updates, 1 plain."""
+    sys.path.insert(0, ROOT)
+    import bench
+    steps = 4
+    launches = {"c2p": 1, "flux_x": 3, "flux_y": 3, "flux_z": 3, "uct_x": 3, "uct_y": 3,
+                "uct_z": 3, "update": 1, "update_c2p": 2, "dt": 1}
+    kernels = {k: {"launches": v * steps} for k, v in launches.items()}
+    fp64 = (144 + 3 * 152 * 2 + 488 + 9 * 88 + (352 + 416) + 336)
+    mixed = (112 + 3 * 80 * 2 + 256 + 9 * 56 + (260 + 324) + 276)
+    assert bench.step_bytes_with_intermediates(kernels, steps, "fp64") == pytest.approx(fp64)
+    assert bench.step_bytes_with_intermediates(kernels, steps, "mixed") == pytest.approx(mixed)
+    # without the fusion the plain update runs every stage at its 3-stage average
+    plain = {k: {"launches": v * steps} for k, v in launches.items() if k != "update_c2p"}
+    plain["update"]["launches"] = 3 * steps
+    plain["c2p"]["launches"] = 3 * steps
+    assert bench.step_bytes_with_intermediates(plain, steps, "fp64") == pytest.approx(
+        3 * 144 + 3 * 152 * 2 + 488 + 9 * 88 + 944)
