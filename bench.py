@@ -53,9 +53,9 @@ STEP_BYTES_RK2 = 352.0
 # the stage's input state (64 B) and, in stages 2 and 3, U^n (64 B), writes
 # the stage's output (64 B): (128 + 192 + 192)/3.  c2p: reads the state and W,
 # writes W.  The flux and UCT passes touch no state array beyond the normal
-# face B (their operands are intermediates).  The roofline's achieved
-# bandwidth and fraction use these bytes.
-STATE_BYTES = {"c2p": 80.0, "flux_x": 8.0, "flux_y": 8.0, "flux_z": 8.0,
+# face B (their operands are intermediates; flux_xy reads two of them).  The
+# roofline's achieved bandwidth and fraction use these bytes.
+STATE_BYTES = {"c2p": 80.0, "flux_xy": 16.0, "flux_z": 8.0,
                "uct_x": 16.0, "uct_y": 16.0, "uct_z": 16.0, "update": 512.0 / 3,
                "update_c2p": 176.0}
 # With the fused update + inversion (stages 1 and 2: 128 + 16 and 192 + 16 B,
@@ -64,41 +64,42 @@ STATE_BYTES_FUSED_UPDATE = 192.0
 
 # Bytes and FP64/FP32 arithmetic operations per unit (cell, face or edge) of
 # each kernel class with its intermediates, for the plain FP64 form and the
-# mixed form, averaged over the class's launches in one step (reported beside
-# the state-byte roofline).  Bytes: every array element the kernel must read
-# or write, once.  flux: 7 primitives + normal B
-# in, 5 fluxes + a+- + 4 face velocities out (the z pass of stage 1 also reads
-# the x and y speeds for the CFL sum: (184 + 152 + 152)/3).  uct_k (one edge
+# mixed form (FP32 primitives, face arrays and face-B copies), averaged over
+# the class's launches in one step (reported beside the state-byte roofline).
+# Bytes: every array element the kernel must read or write, once.  flux_xy
+# (per cell: its x and its y face): the 8 primitives and the two normal face B
+# in, per face 5 fluxes + a+- + 4 face velocities out.  flux_z: 7 primitives
+# + normal B in, 11 face arrays out (the pass of stage 1 also reads the x and
+# y speeds for the CFL sum: (184 + 152 + 152)/3).  uct_k (one edge
 # orientation): the 4 velocities of the P faces, B_P and B_Q, and a+- of the
-# P and Q faces in, E_k out.  update: stage 1 reads 15 fluxes, 3 edge fields
-# and U^n and writes the RK register; stages 2 and 3 also read U^n ((272 +
-# 336 + 336)/3).  Flops: adds, multiplies, divides and square roots of the
-# formulas (FMA = 2), MP5 counted on its limiter path (49 per call, 14 calls
-# per face, 12 per edge).
+# P and Q faces in, E_k (FP64) out.  c2p: the state and W in; the primitives,
+# W (and, mixed, the FP32 face-B copies) out.  update: stage 1 reads 15
+# fluxes, 3 edge fields and U^n and writes the RK register; stages 2 and 3
+# also read U^n ((272 + 336 + 336)/3).  Flops: adds, multiplies, divides and
+# square roots of the formulas (FMA = 2), MP5 counted on its limiter path (49
+# per call, 14 calls per face, 12 per edge).
 KERNEL_UNITS = {
     # class: (bytes fp64, bytes mixed, flops per unit)
-    "c2p": (144.0, 112.0, 200.0),
-    "flux_x": (152.0, 80.0, 940.0),
-    "flux_y": (152.0, 80.0, 940.0),
-    "flux_z": (488.0 / 3, 256.0 / 3, 940.0),
-    "uct_x": (88.0, 56.0, 640.0),
-    "uct_y": (88.0, 56.0, 640.0),
-    "uct_z": (88.0, 56.0, 640.0),
+    "c2p": (144.0, 124.0, 200.0),
+    "flux_xy": (256.0, 128.0, 1880.0),
+    "flux_z": (488.0 / 3, 244.0 / 3, 940.0),
+    "uct_x": (88.0, 48.0, 640.0),
+    "uct_y": (88.0, 48.0, 640.0),
+    "uct_z": (88.0, 48.0, 640.0),
     "update": (944.0 / 3, 764.0 / 3, 80.0),
     # the update fused with the next stage's inversion (stages 1 and 2): also
-    # writes the primitives (FP64, or FP32 in the mixed form) and reads and
-    # writes W
-    "update_c2p": ((272.0 + 336.0) / 2 + 80.0, (212.0 + 276.0) / 2 + 48.0, 280.0),
+    # writes the primitives (FP64, or FP32 in the mixed form, with the FP32
+    # face-B copies) and reads and writes W
+    "update_c2p": ((272.0 + 336.0) / 2 + 80.0, (212.0 + 276.0) / 2 + 60.0, 280.0),
 }
 # the plain update in stage 3 only (when stages 1 and 2 run fused)
 KERNEL_UNITS_FUSED_UPDATE = (336.0, 276.0, 80.0)
 # rocprofv3 kernel names of each class's FP64 launches in one step (name,
 # launches per step), for the HBM traffic read from the profiles (the mixed
-# form's names have float for double)
+# form's names have float for double, and the x-y flux kernel's tile is 64x8)
 PROFILED_KERNEL = {
     "c2p": [("k_c2p<false, false, false>", 1)],
-    "flux_x": [("k_flux<0, double, false, false, 0, true>", 3)],
-    "flux_y": [("k_flux<1, double, false, false, 0, true>", 3)],
+    "flux_xy": [("k_flux_xy<double, false, 0, 4>", 3)],
     "flux_z": [("k_flux<2, double, true, false, 0, true>", 1),
                ("k_flux<2, double, false, false, 0, true>", 2)],
     "uct_x": [("k_uct<0, double, 0, true>", 3)],
@@ -107,6 +108,15 @@ PROFILED_KERNEL = {
     "update": [("k_update<3, double>", 1)],
     "update_c2p": [("k_update_c2p<1, double, false>", 1), ("k_update_c2p<2, double, false>", 1)],
 }
+
+
+def profiled_name(name, mixed):
+    """The rocprofv3 name of an FP64 kernel's launch in the given form."""
+    if not mixed:
+        return name
+    if name.startswith("k_flux_xy<"):
+        return "k_flux_xy<float, false, 0, 8>"
+    return name.replace("double", "float")
 
 
 KERNEL_SOURCES = ("srmhd_kernels.hip", "srmhd_kernels.hpp", "srmhd_phys.hpp")
@@ -139,9 +149,8 @@ def profiled_traffic(kernel_cls, workload):
             if line.startswith("traffic_bytes_per_launch "):
                 name, val = line[len("traffic_bytes_per_launch "):].rsplit(":", 1)
                 got[name.strip()] = int(val)
-        parts = PROFILED_KERNEL[kernel_cls]
-        if workload.endswith("mixed"):
-            parts = [(k.replace("double", "float"), w) for k, w in parts]
+        parts = [(profiled_name(k, workload.endswith("mixed")), w)
+                 for k, w in PROFILED_KERNEL[kernel_cls]]
         if all(k in got for k, _ in parts):
             return int(sum(got[k] * w for k, w in parts) / sum(w for _, w in parts))
     return None
@@ -478,9 +487,11 @@ def main():
         gbs_inter = bytes_with_inter / avg_s / 1e9
         tfl = flops_per / avg_s / 1e12
         fpeak = FP32_PEAK_TFLOPS if (args.precision == "mixed" and dom.startswith("flux")) else FP64_PEAK_TFLOPS
-        # the roof that binds is the one with the larger minimum time (the
-        # kernel's own traffic, intermediates included, decides it)
-        if bytes_with_inter / (HBM_PEAK_GBS * 1e9) >= flops_per / (fpeak * 1e12):
+        # the roof that binds is the one with the larger minimum time for the
+        # kernel's algorithmic bytes (the state arrays it must touch) and its
+        # algorithmic flops; a pass whose operands are all intermediates (the
+        # face fluxes) is bound by its arithmetic
+        if bytes_per / (HBM_PEAK_GBS * 1e9) >= flops_per / (fpeak * 1e12):
             roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None}
         else:

@@ -266,15 +266,16 @@ int srmhd_halo_unpack(srmhd_ctx *ctx, int side, const double *buf);
 
 /* Per-kernel timing with HIP events recorded on the context's stream around
  * every launch (adds a small host/queue overhead per launch; off by
- * default).  Classes, in order: 0 inversion, 1-3 face flux x/y/z, 4-6 UCT
- * edge fields E_x/E_y/E_z, 7 RK update, 8 timestep, 9 RK update fused with
- * the inversion of its result for the next stage (periodic boxes without HO,
- * previous-W or cold guess; class 0 then runs only where no stage before
- * inverted the state) (the learned guess's inference is part of class 0).
+ * default).  Classes, in order: 0 inversion, 1 face fluxes of the x and y
+ * faces (one kernel), 2 face fluxes of the z faces, 3-5 UCT edge fields
+ * E_x/E_y/E_z, 6 RK update, 7 timestep, 8 RK update fused with the inversion
+ * of its result for the next stage (periodic boxes without HO, previous-W or
+ * cold guess; class 0 then runs only where no stage before inverted the
+ * state) (the learned guess's inference is part of class 0).
  * srmhd_get_kernel_times syncs and
  * returns the accumulated milliseconds and launch counts since timing was
  * last enabled (ms, launches: host arrays of SRMHD_NKCLASS). */
-#define SRMHD_NKCLASS 10
+#define SRMHD_NKCLASS 9
 int srmhd_kernel_timing(srmhd_ctx *ctx, int enable);
 int srmhd_get_kernel_times(srmhd_ctx *ctx, double *ms, long *launches);
 

@@ -338,9 +338,9 @@ def srmhd_mlp_adam(params, w_bf16, m, v, grad, n, lr, beta1, beta2, eps, t, stre
                                 _vp(stream)))
 
 
-NKCLASS = 10
-KCLASS_NAMES = ["c2p", "flux_x", "flux_y", "flux_z", "uct_x", "uct_y", "uct_z",
-                "update", "dt", "update_c2p"]
+NKCLASS = 9
+KCLASS_NAMES = ["c2p", "flux_xy", "flux_z", "uct_x", "uct_y", "uct_z", "update", "dt",
+                "update_c2p"]
 
 
 def srmhd_kernel_timing(ctx, enable):

@@ -215,8 +215,9 @@ int rec_kind(const srmhd_ctx* c) {
 template <typename TS>
 void stage_flux(srmhd_ctx* c, const StageState& st, bool cfl) {
   const bool stats = c->cfg.collect_stats != 0;
+  FluxArgs<TS> args[3];
   for (int d = 0; d < 3; ++d) {
-    FluxArgs<TS> a;
+    FluxArgs<TS>& a = args[d];
     a.g = c->g;
     for (int n = 0; n < 8; ++n)
       a.prim[n] = c->mixed ? (const TS*)c->prim32[n] : (const TS*)c->prim64[n];
@@ -234,9 +235,13 @@ void stage_flux(srmhd_ctx* c, const StageState& st, bool cfl) {
     a.gam = c->cfg.gamma_ad;
     a.riemann = c->cfg.riemann;
     a.counters = c->counters;
-    KTimer kt(c, 1 + d);
-    launch_flux<TS>(d, a, cfl && d == 2, stats, rec_kind(c), c->stream);
   }
+  {
+    KTimer kt(c, 1);
+    launch_flux_xy<TS>(args[0], args[1], stats, rec_kind(c), c->stream);
+  }
+  KTimer kt(c, 2);
+  launch_flux_z<TS>(args[2], cfl, stats, rec_kind(c), c->stream);
 }
 
 C2PArgs c2p_args(srmhd_ctx* c, const StageState& st, double* const* prim64, float* const* prim32,
@@ -257,7 +262,7 @@ void stage_uct_update(srmhd_ctx* c, const StageState& st, int stage, double* con
       a.e[d] = c->edge[d];
     }
     for (int k = 0; k < 3; ++k) {
-      KTimer kt(c, 4 + k);
+      KTimer kt(c, 3 + k);
       launch_uct<TS>(a, k, rec_kind(c), c->stream);
     }
   }
@@ -281,10 +286,10 @@ void stage_uct_update(srmhd_ctx* c, const StageState& st, int stage, double* con
     // the next stage's inversion of this stage's output
     const C2PArgs p = c2p_args(c, StageState{}, c->mixed ? nullptr : c->prim64,
                                c->mixed ? c->prim32 : nullptr, guess_code(c));
-    KTimer kt(c, 9);
+    KTimer kt(c, 8);
     launch_update_c2p<TS>(stage, u, p, c->cfg.collect_stats != 0, c->stream);
   } else {
-    KTimer kt(c, 7);
+    KTimer kt(c, 6);
     launch_update<TS>(stage, u, c->cfg.high_order != 0, c->stream);
   }
 }
@@ -379,7 +384,7 @@ void stage_first_half(srmhd_ctx* c, int stage) {
 void stage_second_half(srmhd_ctx* c, int stage, double* const* rhs_out, const double* amax_in) {
   const StageState st = stage_state(c, stage);
   if (stage == 1) {
-    KTimer kt(c, 8);
+    KTimer kt(c, 7);
     launch_dt(c->sc, c->cfg.cfl, c->cfg.dt_fixed, amax_in, c->stream);
   }
   // stages 1 and 2 (the last stage writes into U^n's arrays, which its

@@ -556,13 +556,15 @@ void launch_harvest(const HarvestArgs& a, hipStream_t s) {
 // states of v_DIR and v_{DIR+1}, the two velocity components that the edge
 // field E_{DIR+2} needs at these faces.  With CFL, also the workgroup max of sum_d max(a+,a-)_d/dx_d
 // (needs the other two directions' speeds already stored).
-// Tile per direction: 64x4x1 for x and y; for z 64x1x4 in FP64 and 64x1x8
-// in FP32 (the wavefronts of a z tile share stencil planes).  Measured at
-// 256^3: the FP64 z tile takes 3% off the z pass, the FP32 one 20%; taller
-// FP64 tiles (64x16x1 for y, 64x1x8 or 64x1x16 for z) were slower.  STAGED:
-// the stencil operands come from LDS (Stage); a box thinner than the z tile
-// (nz = 1: a 2D run) takes the z pass unstaged on 64x4x1 tiles, its operands
-// read directly through the periodic stencil indices.
+// The x and y faces run in one kernel (k_flux_xy below: the primitives of a
+// 64x4 (FP64) or 64x8 (FP32) tile and its x and y halos staged once, 3% off
+// the FP64 step against two passes that staged them twice); the z faces in
+// k_flux<2> on 64x1x4 tiles in FP64 and 64x1x8 in FP32 (the wavefronts of a
+// z tile share stencil planes; at 256^3 the FP64 z tile took 3% off the z
+// pass, the FP32 one 20%; 64x1x8 or 64x1x16 FP64 tiles were slower).
+// STAGED: the stencil operands come from LDS (Stage); a box thinner than the
+// z tile (nz = 1: a 2D run) takes the z pass unstaged on 64x4x1 tiles, its
+// operands read directly through the periodic stencil indices.
 template <int DIR, typename TS, bool STAGED = true>
 struct FluxTile : Tile<(DIR == 2 && STAGED) ? 1 : 4,
                        (DIR == 2 && STAGED) ? (sizeof(TS) == 4 ? 8 : 4) : 1> {};
@@ -617,39 +619,15 @@ struct Stage {
   }
 };
 
-template <int DIR, typename TS, bool CFL, bool STATS, int REC, bool STAGED>
-__global__ __launch_bounds__((FluxTile<DIR, TS, STAGED>::kThreads)) void k_flux(FluxArgs<TS> a) {
+// One face of direction DIR at tile cell c: REC of the seven primitives the
+// face reads (val(n, m): stencil point m, offset m - 2, of rho, v_n, v_t1,
+// v_t2, p, B_t1, B_t2), the first-order fallback, the face physics and the
+// HLL/LLF flux; writes the face arrays and returns a+ and a-.
+template <int DIR, typename TS, int REC, typename Val>
+__device__ __forceinline__ void flux_face(const FluxArgs<TS>& a, const Cell& c, Val&& val, int& nfb,
+                                          TS& ap_out, TS& am_out) {
   using T = TS;
-  using Tl = FluxTile<DIR, TS, STAGED>;
-  using St = Stage<DIR, Tl::kY, Tl::kZ>;
   constexpr int T1 = (DIR + 1) % 3, T2 = (DIR + 2) % 3;
-  __shared__ unsigned s_cnt[CNT_N];
-  __shared__ double s_max[16];
-  __shared__ TS s_q[STAGED ? 7 : 1][STAGED ? St::N : 1];  // rho, v_n, v_t1, v_t2, p, B_t1, B_t2
-  BlockCounters bc;
-  if (STATS) bc.init(s_cnt);
-  const Cell c = cell_of_tile<Tl::kY, Tl::kZ, kStencilWaveX<TS>>(a.g);
-  const TS* q[7] = {a.prim[0], a.prim[1 + DIR], a.prim[1 + T1], a.prim[1 + T2],
-                    a.prim[4], a.prim[5 + T1],  a.prim[5 + T2]};
-  if constexpr (STAGED) {
-    St::for_each(a.g, c, [&](int e, int id) {
-#pragma unroll
-      for (int n = 0; n < 7; ++n) s_q[n][e] = q[n][id];
-    });
-    __syncthreads();
-  }
-  int nfb = 0;
-  double cfl_sum = 0.0;
-  const bool inner = c.valid && interior_plane(a.g, c.k);
-  if (c.valid) {
-    // stencil point m (offset m - 2) of primitive n
-    int idx[6];
-    if constexpr (!STAGED) stencil6(a.g, c, DIR, idx);
-    const int b = STAGED ? St::base(c) : 0;
-    auto val = [&](int n, int m) -> T {
-      if constexpr (STAGED) return s_q[n][b + m * St::kStride];
-      else return q[n][idx[m]];
-    };
     FaceState<T> L, R;
     auto rec = [&](int n, T& l, T& r) {
       if (REC == kRecMc)  // the outer two stencil values are not read
@@ -690,6 +668,8 @@ __global__ __launch_bounds__((FluxTile<DIR, TS, STAGED>::kThreads)) void k_flux(
       ap = fmax(T(0), fmax(eL.lp, eR.lp));
       am = fmax(T(0), fmax(-eL.lm, -eR.lm));
     }
+    ap_out = ap;
+    am_out = am;
     const T sum = ap + am;
     T F[5];
     if (sum > T(0)) {
@@ -711,6 +691,43 @@ __global__ __launch_bounds__((FluxTile<DIR, TS, STAGED>::kThreads)) void k_flux(
     a.fv[1][c.id] = L.vt1;
     a.fv[2][c.id] = R.vn;
     a.fv[3][c.id] = R.vt1;
+}
+
+template <int DIR, typename TS, bool CFL, bool STATS, int REC, bool STAGED>
+__global__ __launch_bounds__((FluxTile<DIR, TS, STAGED>::kThreads)) void k_flux(FluxArgs<TS> a) {
+  using T = TS;
+  using Tl = FluxTile<DIR, TS, STAGED>;
+  using St = Stage<DIR, Tl::kY, Tl::kZ>;
+  constexpr int T1 = (DIR + 1) % 3, T2 = (DIR + 2) % 3;
+  __shared__ unsigned s_cnt[CNT_N];
+  __shared__ double s_max[16];
+  __shared__ TS s_q[STAGED ? 7 : 1][STAGED ? St::N : 1];  // rho, v_n, v_t1, v_t2, p, B_t1, B_t2
+  BlockCounters bc;
+  if (STATS) bc.init(s_cnt);
+  const Cell c = cell_of_tile<Tl::kY, Tl::kZ, kStencilWaveX<TS>>(a.g);
+  const TS* q[7] = {a.prim[0], a.prim[1 + DIR], a.prim[1 + T1], a.prim[1 + T2],
+                    a.prim[4], a.prim[5 + T1],  a.prim[5 + T2]};
+  if constexpr (STAGED) {
+    St::for_each(a.g, c, [&](int e, int id) {
+#pragma unroll
+      for (int n = 0; n < 7; ++n) s_q[n][e] = q[n][id];
+    });
+    __syncthreads();
+  }
+  int nfb = 0;
+  double cfl_sum = 0.0;
+  const bool inner = c.valid && interior_plane(a.g, c.k);
+  if (c.valid) {
+    // stencil point m (offset m - 2) of primitive n
+    int idx[6];
+    if constexpr (!STAGED) stencil6(a.g, c, DIR, idx);
+    const int b = STAGED ? St::base(c) : 0;
+    auto val = [&](int n, int m) -> T {
+      if constexpr (STAGED) return s_q[n][b + m * St::kStride];
+      else return q[n][idx[m]];
+    };
+    T ap, am;
+    flux_face<DIR, TS, REC>(a, c, val, nfb, ap, am);
     if (CFL && inner) {
       // sum over d = 0, 1, 2 in that order; the other directions' speeds are
       // apm_other = {a+_T1, a-_T1, a+_T2, a-_T2}
@@ -739,41 +756,110 @@ __global__ __launch_bounds__((FluxTile<DIR, TS, STAGED>::kThreads)) void k_flux(
 }
 
 template <typename TS, int REC, bool ZSTAGED>
-void launch_flux_rec(int dir, const FluxArgs<TS>& a, bool cfl, bool stats, hipStream_t s) {
-#define SRMHD_FLUX(D, C, S, G)                                                                  \
-  hipLaunchKernelGGL((k_flux<D, TS, C, S, REC, G>),                                             \
-                     (tile_grid<FluxTile<D, TS, G>::kY, FluxTile<D, TS, G>::kZ>(a.g)),          \
-                     (tile_block<FluxTile<D, TS, G>::kY, FluxTile<D, TS, G>::kZ>()), 0, s, a)
-  if (dir == 0) {
-    if (stats) SRMHD_FLUX(0, false, true, true); else SRMHD_FLUX(0, false, false, true);
-  } else if (dir == 1) {
-    if (stats) SRMHD_FLUX(1, false, true, true); else SRMHD_FLUX(1, false, false, true);
+void launch_flux_z_rec(const FluxArgs<TS>& a, bool cfl, bool stats, hipStream_t s) {
+#define SRMHD_FLUX(C, S)                                                                        \
+  hipLaunchKernelGGL((k_flux<2, TS, C, S, REC, ZSTAGED>),                                       \
+                     (tile_grid<FluxTile<2, TS, ZSTAGED>::kY, FluxTile<2, TS, ZSTAGED>::kZ>(a.g)), \
+                     (tile_block<FluxTile<2, TS, ZSTAGED>::kY, FluxTile<2, TS, ZSTAGED>::kZ>()), 0, s, a)
+  if (cfl) {
+    if (stats) SRMHD_FLUX(true, true); else SRMHD_FLUX(true, false);
   } else {
-    if (cfl) {
-      if (stats) SRMHD_FLUX(2, true, true, ZSTAGED); else SRMHD_FLUX(2, true, false, ZSTAGED);
-    } else {
-      if (stats) SRMHD_FLUX(2, false, true, ZSTAGED); else SRMHD_FLUX(2, false, false, ZSTAGED);
-    }
+    if (stats) SRMHD_FLUX(false, true); else SRMHD_FLUX(false, false);
   }
 #undef SRMHD_FLUX
 }
 
 template <typename TS, int REC>
-void launch_flux_rec(int dir, const FluxArgs<TS>& a, bool cfl, bool stats, hipStream_t s) {
-  if (dir == 2 && a.g.nz < FluxTile<2, TS>::kZ)
-    launch_flux_rec<TS, REC, false>(dir, a, cfl, stats, s);
+void launch_flux_z_rec(const FluxArgs<TS>& a, bool cfl, bool stats, hipStream_t s) {
+  if (a.g.nz < FluxTile<2, TS>::kZ)
+    launch_flux_z_rec<TS, REC, false>(a, cfl, stats, s);
   else
-    launch_flux_rec<TS, REC, true>(dir, a, cfl, stats, s);
+    launch_flux_z_rec<TS, REC, true>(a, cfl, stats, s);
 }
 
 template <typename TS>
-void launch_flux(int dir, const FluxArgs<TS>& a, bool cfl, bool stats, int rec, hipStream_t s) {
-  if (rec == kRecMc) launch_flux_rec<TS, kRecMc>(dir, a, cfl, stats, s);
-  else if (rec == kRecMp5Point) launch_flux_rec<TS, kRecMp5Point>(dir, a, cfl, stats, s);
-  else launch_flux_rec<TS, kRecMp5>(dir, a, cfl, stats, s);
+void launch_flux_z(const FluxArgs<TS>& a, bool cfl, bool stats, int rec, hipStream_t s) {
+  if (rec == kRecMc) launch_flux_z_rec<TS, kRecMc>(a, cfl, stats, s);
+  else if (rec == kRecMp5Point) launch_flux_z_rec<TS, kRecMp5Point>(a, cfl, stats, s);
+  else launch_flux_z_rec<TS, kRecMp5>(a, cfl, stats, s);
 }
-template void launch_flux<double>(int, const FluxArgs<double>&, bool, bool, int, hipStream_t);
-template void launch_flux<float>(int, const FluxArgs<float>&, bool, bool, int, hipStream_t);
+template void launch_flux_z<double>(const FluxArgs<double>&, bool, bool, int, hipStream_t);
+template void launch_flux_z<float>(const FluxArgs<float>&, bool, bool, int, hipStream_t);
+
+// Primitive of stencil array n (rho, v_n, v_t1, v_t2, p, B_t1, B_t2) for the
+// faces of direction dir, in the order rho, vx, vy, vz, p, Bx, By, Bz.
+__host__ __device__ constexpr int face_prim(int dir, int n) {
+  return n == 0 ? 0 : n == 4 ? 4 : n <= 3 ? 1 + (dir + n - 1) % 3 : 5 + (dir + n - 4) % 3;
+}
+
+// The x and the y faces of a 64 x BY tile in one pass: the eight primitives
+// are staged once over the tile plus the REC halo in x and y ((64 + 5) x
+// (BY + 5) cells, offsets -2..+3; the corners are staged too and not read),
+// then each lane evaluates its x face and its y face (flux_face).  Measured
+// at 512^3 against two staged passes: FP64 BY = 4 -10% (8: -5%, 16: +6%),
+// FP32 BY = 8 -8% (4: -3%, 16: -1%).
+template <typename TS, bool STATS, int REC, int BY>
+__global__ __launch_bounds__(kBlockX * BY) void k_flux_xy(FluxArgs<TS> ax, FluxArgs<TS> ay) {
+  constexpr int EX = kBlockX + 5, EY = BY + 5, N = EX * EY, NT = kBlockX * BY;
+  __shared__ unsigned s_cnt[CNT_N];
+  __shared__ TS s_p[8][N];
+  BlockCounters bc;
+  if (STATS) bc.init(s_cnt);
+  const GridDims& g = ax.g;
+  const Cell c = cell_of_tile<BY, 1, kStencilWaveX<TS>>(g);
+  {
+    const int x0 = c.i - c.li, y0 = c.j - c.lj, z = c.k - c.lk;
+    if (x0 < g.nx && y0 < g.ny && z < g.nz) {  // not a padding tile
+      const int tid = (int)threadIdx.x + kBlockX * (int)threadIdx.y;
+      const size_t zoff = (size_t)z * g.ny * g.nx;
+      for (int e = tid; e < N; e += NT) {
+        const int gx = wrap_index(x0 - 2 + e % EX, g.nx);
+        const int gy = wrap_index(y0 - 2 + e / EX, g.ny);
+        const int id = (int)(zoff + (size_t)gy * g.nx + gx);
+#pragma unroll
+        for (int n = 0; n < 8; ++n) s_p[n][e] = ax.prim[n][id];
+      }
+    }
+    __syncthreads();
+  }
+  int nfb = 0;
+  const bool inner = c.valid && interior_plane(g, c.k);
+  if (c.valid) {
+    const int bxs = (c.lj + 2) * EX + c.li;  // x stencil point m: (li + m, lj + 2)
+    const int bys = c.lj * EX + c.li + 2;    // y stencil point m: (li + 2, lj + m)
+    TS ap, am;
+    flux_face<0, TS, REC>(ax, c, [&](int n, int m) -> TS { return s_p[face_prim(0, n)][bxs + m]; },
+                          nfb, ap, am);
+    flux_face<1, TS, REC>(ay, c,
+                          [&](int n, int m) -> TS { return s_p[face_prim(1, n)][bys + m * EX]; },
+                          nfb, ap, am);
+  }
+  if (STATS) {
+    bc.add_uniform(CNT_FALLBACK, inner ? (unsigned)nfb : 0u);
+    bc.flush(ax.counters);
+  }
+}
+
+template <typename TS>
+void launch_flux_xy(const FluxArgs<TS>& ax, const FluxArgs<TS>& ay, bool stats, int rec,
+                    hipStream_t s) {
+  constexpr int BY = sizeof(TS) == 8 ? 4 : 8;
+#define SRMHD_FXY(ST, R)                                                                   \
+  hipLaunchKernelGGL((k_flux_xy<TS, ST, R, BY>), (tile_grid<BY, 1>(ax.g)),                 \
+                     (tile_block<BY, 1>()), 0, s, ax, ay)
+  if (rec == kRecMc) {
+    if (stats) SRMHD_FXY(true, kRecMc); else SRMHD_FXY(false, kRecMc);
+  } else if (rec == kRecMp5Point) {
+    if (stats) SRMHD_FXY(true, kRecMp5Point); else SRMHD_FXY(false, kRecMp5Point);
+  } else {
+    if (stats) SRMHD_FXY(true, kRecMp5); else SRMHD_FXY(false, kRecMp5);
+  }
+#undef SRMHD_FXY
+}
+template void launch_flux_xy<double>(const FluxArgs<double>&, const FluxArgs<double>&, bool, int,
+                                     hipStream_t);
+template void launch_flux_xy<float>(const FluxArgs<float>&, const FluxArgs<float>&, bool, int,
+                                    hipStream_t);
 
 // ------------------------------------------------------------------- UCT
 // Edge field E_K at (+1/2 along P, +1/2 along Q), (P, Q, K) cyclic, in FP64:

@@ -170,8 +170,13 @@ void launch_harvest(const HarvestArgs& a, hipStream_t s);
 // rec: kRecMp5, kRecMc or kRecMp5Point (srmhd_phys.hpp).  Update stages: 0 =
 // L(U) only, 1..3 = SSP-RK3 stages, 4 = second (last) SSP-RK2 stage; ho:
 // sixth-order DER.
+// The x and the y faces in one pass (primitives staged once per tile).
 template <typename TS>
-void launch_flux(int dir, const FluxArgs<TS>& a, bool cfl, bool stats, int rec, hipStream_t s);
+void launch_flux_xy(const FluxArgs<TS>& ax, const FluxArgs<TS>& ay, bool stats, int rec,
+                    hipStream_t s);
+// The z faces (cfl: also the CFL maximum of the first stage).
+template <typename TS>
+void launch_flux_z(const FluxArgs<TS>& a, bool cfl, bool stats, int rec, hipStream_t s);
 template <typename TS>
 void launch_uct(const Uct3Args<TS>& a, int k, int rec, hipStream_t s);  // orientation E_k
 template <typename TS>

@@ -48,15 +48,15 @@ def test_workload_label_names_the_timed_scheme():
 def test_step_bytes_with_intermediates():
     """The bytes a step's kernels must move (intermediates included), from the
     launch counts of one SSP-RK3 step with the fused update: 1 inversion,
-    3 x 3 flux passes, 3 x 3 UCT orientations, 2 fused updates, 1 plain."""
+    3 x-y and 3 z flux passes, 3 x 3 UCT orientations, 2 fused updates, 1 plain."""
     sys.path.insert(0, ROOT)
     import bench
     steps = 4
-    launches = {"c2p": 1, "flux_x": 3, "flux_y": 3, "flux_z": 3, "uct_x": 3, "uct_y": 3,
-                "uct_z": 3, "update": 1, "update_c2p": 2, "dt": 1}
+    launches = {"c2p": 1, "flux_xy": 3, "flux_z": 3, "uct_x": 3, "uct_y": 3, "uct_z": 3,
+                "update": 1, "update_c2p": 2, "dt": 1}
     kernels = {k: {"launches": v * steps} for k, v in launches.items()}
-    fp64 = (144 + 3 * 152 * 2 + 488 + 9 * 88 + (352 + 416) + 336)
-    mixed = (112 + 3 * 80 * 2 + 256 + 9 * 56 + (260 + 324) + 276)
+    fp64 = (144 + 3 * 256 + 488 + 9 * 88 + (352 + 416) + 336)
+    mixed = (124 + 3 * 128 + 244 + 9 * 48 + (272 + 336) + 276)
     assert bench.step_bytes_with_intermediates(kernels, steps, "fp64") == pytest.approx(fp64)
     assert bench.step_bytes_with_intermediates(kernels, steps, "mixed") == pytest.approx(mixed)
     # without the fusion the plain update runs every stage at its 3-stage average
@@ -64,4 +64,16 @@ def test_step_bytes_with_intermediates():
     plain["update"]["launches"] = 3 * steps
     plain["c2p"]["launches"] = 3 * steps
     assert bench.step_bytes_with_intermediates(plain, steps, "fp64") == pytest.approx(
-        3 * 144 + 3 * 152 * 2 + 488 + 9 * 88 + 944)
+        3 * 144 + 3 * 256 + 488 + 9 * 88 + 944)
+
+
+def test_profiled_kernel_names_cover_the_timing_classes():
+    """Every timing class of the library except the timestep kernel has
+    algorithmic bytes and rocprofv3 names, in both forms."""
+    sys.path.insert(0, ROOT)
+    import bench
+    from paper_2401_03008_amd import binding as B
+    assert set(B.KCLASS_NAMES) - {"dt"} == set(bench.KERNEL_UNITS)
+    assert bench.profiled_name("k_flux_xy<double, false, 0, 4>", True) == \
+        "k_flux_xy<float, false, 0, 8>"
+    assert bench.profiled_name("k_uct<0, double, 0, true>", True) == "k_uct<0, float, 0, true>"

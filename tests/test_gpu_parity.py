@@ -358,7 +358,7 @@ def test_kernel_timing_counts_launches():
     # stages 1 and 2 invert their output inside the update: one separate
     # inversion and one plain update per step
     assert kt["c2p"][1] == 2 and kt["update_c2p"][1] == 4 and kt["update"][1] == 2
-    assert kt["flux_x"][1] == 6 and kt["dt"][1] == 2
+    assert kt["flux_xy"][1] == 6 and kt["flux_z"][1] == 6 and kt["dt"][1] == 2
     assert kt["uct_x"][1] == 6 and kt["uct_y"][1] == 6 and kt["uct_z"][1] == 6
     assert all(v[0] > 0 for v in kt.values())
     S.close()
