@@ -286,7 +286,7 @@ def cpu_baseline(seconds_target=15.0):
                     break
     except OSError:
         pass
-    v, nsteps, el = rate(8)
+    v, nsteps, el = rate(200)  # about seconds_target of work on all cores
     oracle.set_num_threads(1)
     v1, nsteps1, el1 = rate(3)
     oracle.set_num_threads(cores)
