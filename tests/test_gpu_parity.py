@@ -2,7 +2,9 @@
 the same seeded inputs.  Plain FP64 bar: per-variable L1 relative error
 <= 1e-12 (sum |gpu - oracle| / max(sum |oracle|, N s_q), s_q = v_A for
 velocities, B0 for fields, 1 otherwise); element-wise checks of the spatial
-operator on rough random states and on sampled cells at 256^3."""
+operator on rough random states and on sampled cells at 256^3; at 512^3, the
+benchmark's size and launch configuration, properties that hold at any size
+(invariance along the wave fronts, conservation, div B)."""
 import math
 
 import numpy as np
@@ -228,9 +230,9 @@ def test_step_parity_turbulence_ragged():
 
 # ------------------------------------------------- full size, bench launch shape
 def test_rhs_sampled_cells_256():
-    """Diagonal CPA at 256^3 (the benchmark's size and launch shape): L(U) on
-    2048 sampled cells (including the box corners) against the oracle's
-    per-cell evaluation."""
+    """Diagonal CPA at 256^3 (the FP64 GPU configuration's size; the kernels
+    and tiles of the 512^3 benchmark): L(U) on 2048 sampled cells (including
+    the box corners) against the oracle's per-cell evaluation."""
     n = 256
     prim5, bf, _ = I.cpa(n, diagonal=True)
     S = _solver((n, n, n))
@@ -252,8 +254,62 @@ def test_rhs_sampled_cells_256():
         np.testing.assert_allclose(Rg[:, q], Rr[:, q], rtol=0, atol=tol)
 
 
+def _cpa_on_phases(n, device="cuda"):
+    """The diagonal CPA at t = 0 with every value a function of the phase
+    index (i + j + k) mod n alone: the exact formulas evaluated once per phase
+    (cell centres at 2 pi (r + 3/2) / n, faces at 2 pi (r + 2) / n) and
+    gathered, so the data are exactly invariant under shifts along the wave
+    fronts, such as (i, j, k) -> (i + 1, j - 1, k)."""
+    r = np.arange(n, dtype=np.float64)
+    args = (0.0, 0.0, 0.0, True, 1.0, 1.0, 1.0, 1.0, I.GAMMA_AD, (1.0, 1.0, 1.0))
+    v_c, _ = I._fields_at((r + 1.5) / n, *args)
+    _, b_f = I._fields_at((r + 2.0) / n, *args)
+    a = torch.arange(n, device=device)
+    ph = (a.view(n, 1, 1) + a.view(1, n, 1) + a.view(1, 1, n)) % n  # [k][j][i]
+    tab = lambda t: torch.as_tensor(np.broadcast_to(t, (n,)).copy(), device=device)[ph]
+    one = torch.ones((n, n, n), dtype=torch.float64, device=device)
+    prim5 = [one, tab(v_c[0]), tab(v_c[1]), tab(v_c[2]), one.clone()]
+    bf = [tab(b_f[d]) for d in range(3)]
+    del ph
+    return prim5, bf
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_bench_config_512_shift_invariance(precision):
+    """The benchmark's configuration at 512^3 (diagonal CPA, MP5 + HLL + UCT +
+    SSP-RK3, CFL 0.5, previous-W guess, the fused update + inversion, the
+    timed launch shapes): from data that depend on (i + j + k) mod n only,
+    every cell of every evolved array after 3 steps equals, bit for bit, the
+    cell one step along (1, -1, 0) and along (0, 1, -1) -- each cell's
+    arithmetic sees the same operands whatever tile, wavefront, z-march
+    position or XCD it falls on; the totals are conserved to round-off and
+    div B stays at round-off."""
+    n = 512
+    prim5, bf = _cpa_on_phases(n)
+    S = _solver((n, n, n), precision=precision, collect_stats=False)
+    S.init(prim5, bf)
+    del prim5, bf
+    d0 = S.diagnostics()
+    sx0 = S.cons[1].clone()
+    S.step(3)
+    d1 = S.diagnostics()
+    torch.cuda.synchronize()
+    assert d1["t"] > 0.0 and not torch.equal(S.cons[1], sx0)  # the wave has moved
+    del sx0
+    arrays = [S.cons[q] for q in range(5)] + [S.bface[d] for d in range(3)] + [S.W]
+    for q, A in enumerate(arrays):
+        assert torch.equal(A, torch.roll(A, shifts=(1, -1), dims=(1, 2))), q
+        assert torch.equal(A, torch.roll(A, shifts=(1, -1), dims=(0, 1))), q
+    N = n ** 3
+    scale = [1.1 * N, 1.0 * N, 1.0 * N, 1.0 * N, 6.0 * N, 1.5 * N, 1.5 * N, 1.5 * N]
+    for q in range(8):
+        assert abs(d1["sums"][q] - d0["sums"][q]) <= 1e-13 * scale[q], q
+    assert d1["divb_max"] / n < 1e-12 and d1["step"] == 3 and d1["c2p_failures"] == 0
+    S.close()
+
+
 def test_invariants_256_bench_config():
-    """The benchmark workload itself (diagonal CPA 256^3, FP64, CFL 0.5):
+    """The benchmark workload at 256^3 (diagonal CPA, FP64, CFL 0.5):
     sums of D, S, U, face B conserved to round-off and max |div_h B| stays at
     its initial round-off level over 20 steps; no inversion failures."""
     n = 256
