@@ -274,19 +274,24 @@ def _cpa_on_phases(n, device="cuda"):
     return prim5, bf
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_bench_config_512_shift_invariance(precision):
+SHIFT_FORMS = [("fp64", {}), ("mixed", {}), ("fp64", {"high_order": True}),
+               ("mixed", {"high_order": True}), ("fp64", {"recon": "mc", "time_order": 2})]
+
+
+@pytest.mark.parametrize("precision,scheme", SHIFT_FORMS,
+                         ids=["fp64", "mixed", "fp64-ho", "mixed-ho", "fp64-mc-rk2"])
+def test_bench_config_512_shift_invariance(precision, scheme):
     """The benchmark's configuration at 512^3 (diagonal CPA, MP5 + HLL + UCT +
     SSP-RK3, CFL 0.5, previous-W guess, the fused update + inversion, the
-    timed launch shapes): from data that depend on (i + j + k) mod n only,
-    every cell of every evolved array after 3 steps equals, bit for bit, the
-    cell one step along (1, -1, 0) and along (0, 1, -1) -- each cell's
-    arithmetic sees the same operands whatever tile, wavefront, z-march
-    position or XCD it falls on; the totals are conserved to round-off and
-    div B stays at round-off."""
+    timed launch shapes; and the HO and MC + SSP-RK2 forms the benchmark also
+    times): from data that depend on (i + j + k) mod n only, every cell of
+    every evolved array after 3 steps equals, bit for bit, the cell one step
+    along (1, -1, 0) and along (0, 1, -1) -- each cell's arithmetic sees the
+    same operands whatever tile, wavefront, z-march position or XCD it falls
+    on; the totals are conserved to round-off and div B stays at round-off."""
     n = 512
     prim5, bf = _cpa_on_phases(n)
-    S = _solver((n, n, n), precision=precision, collect_stats=False)
+    S = _solver((n, n, n), precision=precision, collect_stats=False, **scheme)
     S.init(prim5, bf)
     del prim5, bf
     d0 = S.diagnostics()
