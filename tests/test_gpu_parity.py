@@ -275,11 +275,13 @@ def _cpa_on_phases(n, device="cuda"):
 
 
 SHIFT_FORMS = [("fp64", {}), ("mixed", {}), ("fp64", {"high_order": True}),
-               ("mixed", {"high_order": True}), ("fp64", {"recon": "mc", "time_order": 2})]
+               ("mixed", {"high_order": True}), ("fp64", {"recon": "mc", "time_order": 2}),
+               ("mixed", {"recon": "mc", "time_order": 2}), ("fp64", {"riemann": "llf"})]
 
 
 @pytest.mark.parametrize("precision,scheme", SHIFT_FORMS,
-                         ids=["fp64", "mixed", "fp64-ho", "mixed-ho", "fp64-mc-rk2"])
+                         ids=["fp64", "mixed", "fp64-ho", "mixed-ho", "fp64-mc-rk2", "mixed-mc-rk2",
+                              "fp64-llf"])
 def test_bench_config_512_shift_invariance(precision, scheme):
     """The benchmark's configuration at 512^3 (diagonal CPA, MP5 + HLL + UCT +
     SSP-RK3, CFL 0.5, previous-W guess, the fused update + inversion, the
